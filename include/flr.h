@@ -1,0 +1,159 @@
+/*
+ * flr.h - C ABI of the MI355X (gfx950) majorization-minimization solver for
+ * fused lasso regression (FLR).
+ *
+ * Problem (introduction, FLR objective): minimize over b in R^p
+ *   f(b) = 1/2 ||y - X b||^2 + lambda1 sum_j |b_j| + lambda2 sum_{(j,k) in E} |b_j - b_k|
+ * with X an n x p design matrix, y in R^n, lambda1, lambda2 >= 0 and E a set
+ * of unordered index pairs (chain for the standard FLR, q x q lattice for the
+ * two-dimensional FLR, all pairs for the clustered / pairwise fused lasso).
+ *
+ * Method (section 3.1, perturbed objective, majorizer and linear-system
+ * equations; Algorithm 2): every |b_j| and |b_j - b_k| is replaced by
+ * |t| - eps log(1 + |t|/eps) and majorized at the current iterate by a
+ * quadratic; its minimizer solves
+ *   (X^T X + lambda1 A + lambda2 B) b = X^T y,
+ *   A = diag(1/(|b_j| + eps)),  B = Laplacian of E with w_jk = 1/(|b_j - b_k| + eps),
+ * by conjugate gradients preconditioned with M = lambda1 A + lambda2 B,
+ * warm-started at the current iterate (Algorithm 2).  Iteration stops when the
+ * relative change of f falls to tol.  The whole loop runs on the GPU; the host
+ * sees only launch and completion.
+ *
+ * Conventions
+ *  - Every call returns flr_status; no C++ exception crosses this boundary.
+ *  - Pointers named *_host must be host memory; pointers documented as
+ *    "host or device" are classified with hipPointerGetAttributes.
+ *  - The library copies what it needs at creation: the caller may free its
+ *    buffers as soon as flr_create returns.  Handles are owned by the
+ *    library until the matching *_destroy; output buffers are caller-owned.
+ *  - Invalid arguments return FLR_ERR_INVALID_ARG and leave outputs untouched.
+ *  - One thread at a time per problem handle; distinct handles may be used
+ *    concurrently (each has its own device buffers, state and stream).
+ *  - flr_last_error() returns a thread-local message for the last failure.
+ */
+#ifndef FLR_H
+#define FLR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct flr_ctx_s* flr_ctx;         /* one GPU: device id and default stream */
+typedef struct flr_problem_s* flr_problem; /* resident X, y, CSR(E), X^T y, ||X_j||^2, warm start */
+typedef struct flr_server_s* flr_server;   /* continuous-batching serving loop */
+
+typedef enum {
+  FLR_OK = 0,
+  FLR_ERR_INVALID_ARG = 1,
+  FLR_ERR_OUT_OF_MEMORY = 2,
+  FLR_ERR_DEVICE = 3,
+  FLR_ERR_NUMERICAL = 4, /* CG breakdown (p^T Q p <= 0) or a non-finite value inside the loop */
+  FLR_ERR_MAX_ITER = 5,  /* iteration cap reached; outputs hold the last iterate */
+  FLR_ERR_BUSY = 6,      /* handle in use by another thread, or no slot/memory (serving) */
+  FLR_ERR_NOT_READY = 7  /* serving: the ticket has not completed yet */
+} flr_status;
+
+typedef enum { FLR_F64 = 0, FLR_F32 = 1, FLR_BF16 = 2 } flr_dtype;
+
+/* Arithmetic of the inner products with X (the p-scale terms, dot products,
+ * objective and stopping tests are always FP64). */
+typedef enum { FLR_PREC_FP64 = 0, FLR_PREC_MIXED_FP32 = 1 } flr_precision;
+
+/* Preconditioner of the PCG inner solve.  AUTO = the tridiagonal part of
+ * M = lambda1 A + lambda2 B (edges (j-1, j) keep their coupling, every other
+ * edge adds only to the diagonal) - exactly the paper's M for the chain - and
+ * Jacobi diag(Q) when lambda1 = 0, where M is singular. */
+typedef enum { FLR_PRECOND_AUTO = 0, FLR_PRECOND_TRIDIAG = 1, FLR_PRECOND_JACOBI = 2 } flr_precond;
+
+typedef struct {
+  double eps;              /* perturbation; 0 -> 1e-8 (section 5) */
+  double inner_tol;        /* PCG stop ||r|| / ||X^T y||; 0 -> tol (Algorithm 2 uses one delta) */
+  int32_t max_iter;        /* MM iteration cap; 0 -> 10000 (section 5) */
+  int32_t max_cg;          /* PCG steps per MM iteration; 0 -> p */
+  int32_t precision;       /* flr_precision */
+  int32_t preconditioner;  /* flr_precond */
+  const double* warm_start;/* host or device, length p; NULL -> the handle's last beta if
+                              use_last is set and a solve has run, else X_j^T y / X_j^T X_j */
+  int32_t use_last;        /* 1: warm-start from the handle's previous solution */
+  int32_t reserved;
+} flr_solve_opts;
+
+typedef struct {
+  double objective;        /* f at the returned beta, FP64 on the stored instance */
+  double rel_change;       /* last |f_new - f_old| / f_old */
+  double rel_residual;     /* last PCG ||r|| / ||X^T y|| */
+  double seconds;          /* wall time of the solve */
+  int64_t cg_iters;        /* total PCG steps */
+  int32_t mm_iters;        /* MM (outer) iterations */
+  int32_t status;          /* flr_status of this solve */
+} flr_result;
+
+/* Fill opts with the defaults above. */
+void flr_default_opts(flr_solve_opts* opts);
+
+/* Bind a context to GPU `device`.  hip_stream: a hipStream_t to run on, or
+ * NULL for a stream owned by the context. */
+flr_status flr_ctx_create(int device, void* hip_stream, flr_ctx* out);
+void flr_ctx_destroy(flr_ctx ctx);
+
+/* Create a resident problem (problem statement of the introduction).
+ * X: host or device, n x p row-major with row stride ldx >= p elements, in
+ *    x_dtype (FLR_BF16 = uint16 bfloat16 bit patterns).
+ * y: host, length n.  edges: host, 2*m int64 values (pairs (j, k), 0-based);
+ *    stored as a set of unordered pairs (duplicates dropped).
+ * Errors: n, p < 1, ldx < p, non-finite X or y, an edge out of range or a
+ * self-loop -> FLR_ERR_INVALID_ARG; allocation failure -> FLR_ERR_OUT_OF_MEMORY. */
+flr_status flr_create(flr_ctx ctx, const void* X, flr_dtype x_dtype, int64_t n, int64_t p, int64_t ldx,
+                      const double* y, const int64_t* edges, int64_t m, flr_problem* out);
+void flr_destroy(flr_problem h);
+
+/* Solve at (lambda1, lambda2) to relative objective change tol (Algorithm 2).
+ * beta_out_host: length p.  objective_out, iterations_out: nullable.
+ * Errors: lambda < 0 or non-finite, tol <= 0 -> FLR_ERR_INVALID_ARG;
+ * FLR_ERR_MAX_ITER / FLR_ERR_NUMERICAL with beta_out holding the last iterate. */
+flr_status flr_solve(flr_problem h, double lambda1, double lambda2, double tol, double* beta_out_host,
+                     double* objective_out, int32_t* iterations_out);
+
+/* As flr_solve with options.  beta_out: host or device, length p; res nullable. */
+flr_status flr_solve_ex(flr_problem h, double lambda1, double lambda2, double tol, const flr_solve_opts* opts,
+                        double* beta_out, flr_result* res);
+
+/* Solve B (lambda1[i], lambda2[i]) settings on one problem in one launch
+ * sequence: X P and X^T U become B-column products (MFMA), every column keeps
+ * its own scalars, weights, preconditioner and convergence state.
+ * lambda1, lambda2: host, length B.  beta_out: host or device, B x p row-major.
+ * res: nullable host array of B results.  Returns FLR_OK when every column
+ * converged, else the first failing column's status. */
+flr_status flr_solve_grid(flr_problem h, const double* lambda1, const double* lambda2, int32_t B, double tol,
+                          const flr_solve_opts* opts, double* beta_out, flr_result* res);
+
+/* Device footprint of a problem in bytes (what serving admission charges). */
+flr_status flr_problem_footprint(flr_problem h, size_t* bytes);
+int64_t flr_problem_n(flr_problem h);
+int64_t flr_problem_p(flr_problem h);
+int64_t flr_problem_m(flr_problem h);
+
+/* Serving: requests are admitted while the sum of the footprints of problems
+ * in flight stays within hbm_budget_bytes and a slot is free; each slot runs
+ * on its own stream, so solves that arrive while others run overlap on the
+ * device.  Results do not depend on what else runs (fixed reduction trees,
+ * no cross-request atomics). */
+flr_status flr_server_create(flr_ctx ctx, size_t hbm_budget_bytes, int32_t max_slots, flr_server* out);
+flr_status flr_server_submit(flr_server s, flr_problem h, double lambda1, double lambda2, double tol,
+                             const flr_solve_opts* opts, uint64_t* ticket);
+/* blocking = 0: FLR_ERR_NOT_READY until done.  beta_out_host: nullable, length p. */
+flr_status flr_server_poll(flr_server s, uint64_t ticket, int blocking, double* beta_out_host, flr_result* res);
+/* Queue depth, slots in use and bytes admitted. */
+flr_status flr_server_stats(flr_server s, int32_t* queued, int32_t* running, size_t* bytes_in_use);
+void flr_server_destroy(flr_server s);
+
+const char* flr_status_string(flr_status st);
+const char* flr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLR_H */

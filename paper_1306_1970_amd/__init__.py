@@ -1,0 +1,306 @@
+"""Python binding of the MI355X fused-lasso MM solver (``libflr.so``).
+
+Argument marshalling only: every step of the solve runs in the HIP kernels
+behind the C ABI declared in ``include/flr.h``; the functions here carry
+the same names.  Arrays may be numpy arrays (host) or torch tensors (host
+or device; a device tensor is passed by its data pointer and used where it
+lives).  There is no CPU fallback: if the library is missing or no GPU is
+visible, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libflr.so")
+
+FLR_OK, FLR_ERR_INVALID_ARG, FLR_ERR_OUT_OF_MEMORY, FLR_ERR_DEVICE = 0, 1, 2, 3
+FLR_ERR_NUMERICAL, FLR_ERR_MAX_ITER, FLR_ERR_BUSY, FLR_ERR_NOT_READY = 4, 5, 6, 7
+FLR_F64, FLR_F32, FLR_BF16 = 0, 1, 2
+FLR_PREC_FP64, FLR_PREC_MIXED_FP32 = 0, 1
+FLR_PRECOND_AUTO, FLR_PRECOND_TRIDIAG, FLR_PRECOND_JACOBI = 0, 1, 2
+
+# every symbol include/flr.h declares
+EXPORTS = [
+    "flr_default_opts", "flr_ctx_create", "flr_ctx_destroy", "flr_create", "flr_destroy", "flr_solve",
+    "flr_solve_ex", "flr_solve_grid", "flr_problem_footprint", "flr_problem_n", "flr_problem_p", "flr_problem_m",
+    "flr_server_create", "flr_server_submit", "flr_server_poll", "flr_server_stats", "flr_server_destroy",
+    "flr_status_string", "flr_last_error",
+]
+
+
+class FlrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (status_name(status), msg))
+        self.status = status
+
+
+class flr_solve_opts(C.Structure):
+    _fields_ = [("eps", C.c_double), ("inner_tol", C.c_double), ("max_iter", C.c_int32), ("max_cg", C.c_int32),
+                ("precision", C.c_int32), ("preconditioner", C.c_int32), ("warm_start", C.c_void_p),
+                ("use_last", C.c_int32), ("reserved", C.c_int32)]
+
+
+class flr_result(C.Structure):
+    _fields_ = [("objective", C.c_double), ("rel_change", C.c_double), ("rel_residual", C.c_double),
+                ("seconds", C.c_double), ("cg_iters", C.c_int64), ("mm_iters", C.c_int32), ("status", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libflr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FileNotFoundError("libflr.so is not built: run __graft_entry__.build() or "
+                                    "python paper_1306_1970_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32, d = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+        L.flr_default_opts.argtypes = [C.POINTER(flr_solve_opts)]
+        L.flr_ctx_create.argtypes = [C.c_int, vp, C.POINTER(vp)]
+        L.flr_ctx_destroy.argtypes = [vp]
+        L.flr_create.argtypes = [vp, vp, C.c_int, i64, i64, i64, vp, vp, i64, C.POINTER(vp)]
+        L.flr_destroy.argtypes = [vp]
+        L.flr_solve.argtypes = [vp, d, d, d, vp, C.POINTER(d), C.POINTER(i32)]
+        L.flr_solve_ex.argtypes = [vp, d, d, d, C.POINTER(flr_solve_opts), vp, C.POINTER(flr_result)]
+        L.flr_solve_grid.argtypes = [vp, vp, vp, i32, d, C.POINTER(flr_solve_opts), vp, vp]
+        L.flr_problem_footprint.argtypes = [vp, C.POINTER(C.c_size_t)]
+        for f in ("flr_problem_n", "flr_problem_p", "flr_problem_m"):
+            getattr(L, f).argtypes = [vp]
+            getattr(L, f).restype = i64
+        L.flr_server_create.argtypes = [vp, C.c_size_t, i32, C.POINTER(vp)]
+        L.flr_server_submit.argtypes = [vp, vp, d, d, d, C.POINTER(flr_solve_opts), C.POINTER(C.c_uint64)]
+        L.flr_server_poll.argtypes = [vp, C.c_uint64, C.c_int, vp, C.POINTER(flr_result)]
+        L.flr_server_stats.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_size_t)]
+        L.flr_server_destroy.argtypes = [vp]
+        L.flr_status_string.argtypes = [C.c_int]
+        L.flr_status_string.restype = C.c_char_p
+        L.flr_last_error.restype = C.c_char_p
+        for name in EXPORTS:
+            f = getattr(L, name)
+            if f.restype is C.c_int and name not in ("flr_status_string",):
+                f.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def status_name(st: int) -> str:
+    try:
+        return lib().flr_status_string(int(st)).decode()
+    except Exception:  # pragma: no cover
+        return "status %d" % st
+
+
+def last_error() -> str:
+    return lib().flr_last_error().decode()
+
+
+def _check(st, ok=(FLR_OK,)):
+    if st not in ok:
+        raise FlrError(st, last_error())
+    return st
+
+
+def _ptr(a):
+    """Data pointer of a numpy array or torch tensor (None passes through)."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def default_opts(**kw) -> flr_solve_opts:
+    o = flr_solve_opts()
+    lib().flr_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if k == "warm_start":
+            o.warm_start = _ptr(v)
+        else:
+            setattr(o, k, v)
+    return o
+
+
+# ---------------------------------------------------------------------------
+# C ABI, same names
+# ---------------------------------------------------------------------------
+def flr_ctx_create(device: int = 0, hip_stream: int | None = None):
+    out = C.c_void_p()
+    _check(lib().flr_ctx_create(device, hip_stream, C.byref(out)))
+    return out
+
+
+def flr_ctx_destroy(ctx):
+    lib().flr_ctx_destroy(ctx)
+
+
+def flr_create(ctx, X, x_dtype: int, n: int, p: int, ldx: int, y, edges, m: int):
+    out = C.c_void_p()
+    _check(lib().flr_create(ctx, _ptr(X), x_dtype, n, p, ldx, _ptr(y), _ptr(edges) if m else None, m,
+                            C.byref(out)))
+    return out
+
+
+def flr_destroy(h):
+    lib().flr_destroy(h)
+
+
+def flr_solve(h, lambda1, lambda2, tol, beta_out):
+    f = C.c_double()
+    it = C.c_int32()
+    st = lib().flr_solve(h, lambda1, lambda2, tol, _ptr(beta_out), C.byref(f), C.byref(it))
+    _check(st, ok=(FLR_OK, FLR_ERR_MAX_ITER, FLR_ERR_NUMERICAL))
+    return st, f.value, it.value
+
+
+def flr_solve_ex(h, lambda1, lambda2, tol, opts, beta_out):
+    res = flr_result()
+    st = lib().flr_solve_ex(h, lambda1, lambda2, tol, C.byref(opts) if opts is not None else None, _ptr(beta_out),
+                            C.byref(res))
+    _check(st, ok=(FLR_OK, FLR_ERR_MAX_ITER, FLR_ERR_NUMERICAL))
+    return st, res
+
+
+def flr_solve_grid(h, lambda1, lambda2, tol, opts, beta_out):
+    l1 = np.ascontiguousarray(lambda1, dtype=np.float64)
+    l2 = np.ascontiguousarray(lambda2, dtype=np.float64)
+    B = int(l1.size)
+    res = (flr_result * B)()
+    st = lib().flr_solve_grid(h, l1.ctypes.data, l2.ctypes.data, B, tol, C.byref(opts) if opts is not None else None,
+                              _ptr(beta_out), C.cast(res, C.c_void_p))
+    _check(st, ok=(FLR_OK, FLR_ERR_MAX_ITER, FLR_ERR_NUMERICAL))
+    return st, list(res)
+
+
+def flr_problem_footprint(h) -> int:
+    b = C.c_size_t()
+    _check(lib().flr_problem_footprint(h, C.byref(b)))
+    return int(b.value)
+
+
+def flr_server_create(ctx, hbm_budget_bytes: int, max_slots: int):
+    out = C.c_void_p()
+    _check(lib().flr_server_create(ctx, hbm_budget_bytes, max_slots, C.byref(out)))
+    return out
+
+
+def flr_server_submit(s, h, lambda1, lambda2, tol, opts=None) -> int:
+    t = C.c_uint64()
+    _check(lib().flr_server_submit(s, h, lambda1, lambda2, tol, C.byref(opts) if opts is not None else None,
+                                   C.byref(t)))
+    return int(t.value)
+
+
+def flr_server_poll(s, ticket: int, blocking: bool, beta_out=None):
+    res = flr_result()
+    st = lib().flr_server_poll(s, ticket, 1 if blocking else 0, _ptr(beta_out), C.byref(res))
+    _check(st, ok=(FLR_OK, FLR_ERR_MAX_ITER, FLR_ERR_NUMERICAL, FLR_ERR_NOT_READY))
+    return st, res
+
+
+def flr_server_stats(s):
+    q, r, b = C.c_int32(), C.c_int32(), C.c_size_t()
+    _check(lib().flr_server_stats(s, C.byref(q), C.byref(r), C.byref(b)))
+    return q.value, r.value, int(b.value)
+
+
+def flr_server_destroy(s):
+    lib().flr_server_destroy(s)
+
+
+# ---------------------------------------------------------------------------
+# small object wrappers
+# ---------------------------------------------------------------------------
+_DT = {FLR_F64: np.float64, FLR_F32: np.float32, FLR_BF16: np.uint16}
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.h = flr_ctx_create(device)
+
+    def close(self):
+        if self.h:
+            flr_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Solution:
+    beta: np.ndarray
+    status: int
+    objective: float
+    mm_iters: int
+    cg_iters: int
+    rel_change: float
+    rel_residual: float
+    seconds: float
+
+
+class Problem:
+    """A resident FLR problem: X (numpy array in its stored dtype, or a
+    device tensor), y (float64), edges (int64 pairs)."""
+
+    def __init__(self, ctx: Context, X, x_dtype: int, y, edges):
+        self.ctx = ctx
+        if hasattr(X, "data_ptr"):
+            n, p = int(X.shape[0]), int(X.shape[1])
+            ldx = int(X.stride(0))
+            self._X = X
+        else:
+            X = np.ascontiguousarray(X, dtype=_DT[x_dtype])
+            n, p = X.shape
+            ldx = p
+            self._X = X
+        yv = np.ascontiguousarray(y, dtype=np.float64)
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.int64).reshape(-1, 2))
+        self.n, self.p, self.m_in = n, p, e.shape[0]
+        self.h = flr_create(ctx.h, self._X, x_dtype, n, p, ldx, yv, e, e.shape[0])
+        self._X = None  # the library holds its own copy
+
+    @classmethod
+    def from_instance(cls, ctx, inst):
+        return cls(ctx, inst.X, inst.dtype, inst.y, inst.edges)
+
+    @property
+    def footprint(self) -> int:
+        return flr_problem_footprint(self.h)
+
+    def solve(self, lam1, lam2, tol=1e-8, out=None, **opts) -> Solution:
+        o = default_opts(**opts)
+        beta = np.zeros(self.p) if out is None else out
+        st, r = flr_solve_ex(self.h, lam1, lam2, tol, o, beta)
+        b = beta if isinstance(beta, np.ndarray) else beta
+        return Solution(b, st, r.objective, r.mm_iters, r.cg_iters, r.rel_change, r.rel_residual, r.seconds)
+
+    def solve_grid(self, lam1, lam2, tol=1e-8, **opts):
+        o = default_opts(**opts)
+        B = len(lam1)
+        beta = np.zeros((B, self.p))
+        st, res = flr_solve_grid(self.h, lam1, lam2, tol, o, beta)
+        return st, beta, [r.as_dict() for r in res]
+
+    def close(self):
+        if self.h:
+            flr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass

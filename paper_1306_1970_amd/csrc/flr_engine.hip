@@ -1,0 +1,516 @@
+// Host engine behind the C ABI of include/flr.h: problem residency, the
+// captured launch rotation, the solve driver and the status plumbing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/flr.h"
+#include "flr_internal.h"
+
+namespace flr {
+hipError_t launch_rotation(const Dims& D, const Bufs& B, int par, int which, hipStream_t st);
+hipError_t launch_setup(const Dims& D, const void* X, const double* y, double* cpart, double* spart, double* c,
+                        double* s, hipStream_t st);
+hipError_t launch_init(const Dims& D, const Bufs& B, const double* warm, int use_warm, hipStream_t st);
+hipError_t launch_check_finite(const void* X, int dtype, int64_t count, int* flag, hipStream_t st);
+}  // namespace flr
+
+using namespace flr;
+
+static thread_local std::string g_last_error;
+
+static flr_status fail(flr_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define HIP_OR_FAIL(expr)                                                                                   \
+  do {                                                                                                      \
+    hipError_t e_ = (expr);                                                                                 \
+    if (e_ != hipSuccess)                                                                                   \
+      return fail(e_ == hipErrorOutOfMemory ? FLR_ERR_OUT_OF_MEMORY : FLR_ERR_DEVICE,                       \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                                       \
+  } while (0)
+
+struct flr_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+};
+
+// Number of A/B/C rounds captured in one graph (3*S launches; S even keeps
+// the state parity fixed per node).
+static constexpr int kRounds = 16;
+
+struct flr_problem_s {
+  flr_ctx ctx = nullptr;
+  Dims D{};
+  Bufs B{};
+  int64_t m = 0;
+  int64_t nnz = 0;
+  double cnorm = 0.0;
+  hipStream_t stream = nullptr;
+  Params* d_prm = nullptr;
+  Params* h_prm = nullptr;  // pinned
+  State* h_state = nullptr; // pinned, 2 slots
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<void*> allocs;
+  size_t footprint = 0;
+  bool has_solution = false;
+  std::mutex busy;
+};
+
+namespace {
+
+template <typename T>
+hipError_t dalloc(flr_problem h, T** p, size_t count) {
+  size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
+  if (e == hipSuccess) {
+    h->allocs.push_back(*p);
+    h->footprint += bytes;
+    e = hipMemsetAsync(*p, 0, bytes, h->stream);
+  }
+  return e;
+}
+
+int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+Dims choose_dims(int64_t n, int64_t p, int dtype) {
+  Dims D{};
+  D.n = n;
+  D.p = p;
+  D.dtype = dtype;
+  const int V = dtype == FLR_F64 ? 2 : dtype == FLR_F32 ? 4 : 8;
+  D.c1 = 256 * V;
+  D.c2 = 64 * V;
+  D.p_pad = round_up(p, D.c1);
+  D.ldx = D.p_pad;
+  D.cb1 = (int32_t)(D.p_pad / D.c1);
+  const int target = 512;
+  int64_t rb1 = std::max<int64_t>(1, (target + D.cb1 - 1) / D.cb1);
+  rb1 = std::min<int64_t>(rb1, std::max<int64_t>(1, n / 4));
+  D.r1 = (int32_t)((n + rb1 - 1) / rb1);
+  D.rb1 = (int32_t)((n + D.r1 - 1) / D.r1);
+  D.cb2 = (int32_t)(D.p_pad / D.c2);
+  int64_t rb2 = std::max<int64_t>(1, (target + D.cb2 - 1) / D.cb2);
+  rb2 = std::min<int64_t>(rb2, std::max<int64_t>(1, n / 4));
+  int64_t r2 = (n + rb2 - 1) / rb2;
+  if (r2 > kMaxR2) r2 = kMaxR2;
+  D.r2 = (int32_t)r2;
+  D.rb2 = (int32_t)((n + r2 - 1) / r2);
+  D.nblk = (int32_t)(D.p_pad / kBlk);
+  D.gridB = std::max(D.cb2 * D.rb2, D.nblk);
+  return D;
+}
+
+bool is_device_ptr(const void* ptr) {
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, ptr) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+}
+
+flr_status build_graph(flr_problem h) {
+  if (h->gexec) return FLR_OK;
+  HIP_OR_FAIL(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t err = hipSuccess;
+  for (int i = 0; i < 3 * kRounds && err == hipSuccess; ++i) err = launch_rotation(h->D, h->B, i & 1, i % 3, h->stream);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(h->stream, &g);
+  if (err != hipSuccess) return fail(FLR_ERR_DEVICE, std::string("capture launch: ") + hipGetErrorString(err));
+  HIP_OR_FAIL(e2);
+  h->graph = g;
+  HIP_OR_FAIL(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
+  return FLR_OK;
+}
+
+flr_status validate_lambdas(double l1, double l2, double tol) {
+  if (!(std::isfinite(l1) && l1 >= 0.0) || !(std::isfinite(l2) && l2 >= 0.0))
+    return fail(FLR_ERR_INVALID_ARG, "lambda1 and lambda2 must be finite and >= 0");
+  if (!(std::isfinite(tol) && tol > 0.0)) return fail(FLR_ERR_INVALID_ARG, "tol must be finite and > 0");
+  return FLR_OK;
+}
+
+// One solve on the problem's stream; beta_out host or device (or nullptr).
+flr_status run_solve(flr_problem h, double l1, double l2, double tol, const flr_solve_opts* o, double* beta_out,
+                     flr_result* res) {
+  auto t0 = std::chrono::steady_clock::now();
+  flr_solve_opts dflt;
+  flr_default_opts(&dflt);
+  if (!o) o = &dflt;
+  if (!(o->eps >= 0.0) || !(o->inner_tol >= 0.0) || o->max_iter < 0 || o->max_cg < 0)
+    return fail(FLR_ERR_INVALID_ARG, "options out of range");
+  const Dims& D = h->D;
+  Params& P = *h->h_prm;
+  P.lam1 = l1;
+  P.lam2 = l2;
+  P.eps = o->eps > 0.0 ? o->eps : 1e-8;
+  P.tol = tol;
+  P.inner_tol = o->inner_tol > 0.0 ? o->inner_tol : tol;
+  P.cnorm = h->cnorm > 0.0 ? h->cnorm : 1.0;
+  P.max_iter = o->max_iter > 0 ? o->max_iter : 10000;
+  P.max_cg = o->max_cg > 0 ? o->max_cg : (int32_t)std::min<int64_t>(D.p, INT32_MAX);
+  int pre = o->preconditioner;
+  if (pre == FLR_PRECOND_AUTO) pre = (l1 > 0.0) ? FLR_PRECOND_TRIDIAG : FLR_PRECOND_JACOBI;
+  if (pre == FLR_PRECOND_TRIDIAG && !(l1 > 0.0))
+    return fail(FLR_ERR_INVALID_ARG, "the tridiagonal preconditioner needs lambda1 > 0 (M is singular otherwise)");
+  P.jacobi = pre == FLR_PRECOND_JACOBI ? 1 : 0;
+  P.mixed = o->precision == FLR_PREC_MIXED_FP32 ? 1 : 0;
+  HIP_OR_FAIL(hipMemcpyAsync(h->d_prm, h->h_prm, sizeof(Params), hipMemcpyHostToDevice, h->stream));
+
+  const double* warm = nullptr;
+  int use_warm = 0;
+  if (o->warm_start) {
+    if (is_device_ptr(o->warm_start)) {
+      warm = o->warm_start;
+    } else {
+      HIP_OR_FAIL(hipMemcpyAsync(h->B.r, o->warm_start, D.p * sizeof(double), hipMemcpyHostToDevice, h->stream));
+      warm = h->B.r;  // staged in the residual buffer; k_init reads it before clearing
+    }
+    use_warm = 1;
+  } else if (o->use_last && h->has_solution) {
+    warm = h->B.x;
+    use_warm = 1;
+  }
+  if (use_warm && warm == h->B.r) {
+    // k_init clears r after reading warm[j] in the same thread: safe element-wise
+  }
+  HIP_OR_FAIL(launch_init(D, h->B, warm, use_warm, h->stream));
+  flr_status gs = build_graph(h);
+  if (gs != FLR_OK) return gs;
+
+  // launch the captured rotation until the state machine reports done; keep
+  // one launch in flight beyond the one being polled
+  const int64_t max_launches = ((int64_t)P.max_iter * ((int64_t)P.max_cg + 2) + 2) / kRounds + 4;
+  int64_t launched = 0;
+  bool done = false;
+  State fin{};
+  while (!done) {
+    if (launched >= max_launches) return fail(FLR_ERR_DEVICE, "solve did not terminate within its launch bound");
+    const int slot = (int)(launched & 1);
+    HIP_OR_FAIL(hipGraphLaunch(h->gexec, h->stream));
+    HIP_OR_FAIL(hipMemcpyAsync(&h->h_state[slot], &h->B.st[0], sizeof(State), hipMemcpyDeviceToHost, h->stream));
+    HIP_OR_FAIL(hipEventRecord(h->ev[slot], h->stream));
+    ++launched;
+    if (launched >= 2) {
+      const int prev = (int)((launched - 2) & 1);
+      HIP_OR_FAIL(hipEventSynchronize(h->ev[prev]));
+      if (h->h_state[prev].phase == PH_DONE) done = true;
+    }
+  }
+  HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+  fin = h->h_state[(launched - 1) & 1];
+  if (beta_out) HIP_OR_FAIL(hipMemcpy(beta_out, h->B.x, D.p * sizeof(double), hipMemcpyDefault));
+  h->has_solution = true;
+  flr_status st = fin.status == ST_OK ? FLR_OK : fin.status == ST_MAX_ITER ? FLR_ERR_MAX_ITER : FLR_ERR_NUMERICAL;
+  if (res) {
+    res->objective = fin.f_new;
+    res->rel_change = fin.rel_change;
+    res->rel_residual = fin.rel_res;
+    res->cg_iters = fin.cg_total;
+    res->mm_iters = fin.mm_iter;
+    res->status = st;
+    res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (st == FLR_ERR_NUMERICAL) g_last_error = "non-finite value or CG breakdown inside the solve";
+  if (st == FLR_ERR_MAX_ITER) g_last_error = "MM iteration cap reached";
+  return st;
+}
+
+}  // namespace
+
+namespace flr {
+// Entry used by the serving loop: the caller already holds the handle.
+flr_status solve_locked(flr_problem h, double l1, double l2, double tol, const flr_solve_opts* o, double* beta_out,
+                        flr_result* res) {
+  flr_status v = validate_lambdas(l1, l2, tol);
+  if (v != FLR_OK) return v;
+  if (hipSetDevice(h->ctx->device) != hipSuccess) return fail(FLR_ERR_DEVICE, "hipSetDevice failed");
+  return run_solve(h, l1, l2, tol, o, beta_out, res);
+}
+std::mutex& problem_mutex(flr_problem h) { return h->busy; }
+size_t problem_footprint(flr_problem h) { return h->footprint; }
+int problem_device(flr_problem h) { return h->ctx->device; }
+void set_last_error(const std::string& s) { g_last_error = s; }
+}  // namespace flr
+
+extern "C" {
+
+void flr_default_opts(flr_solve_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->eps = 1e-8;
+  o->precision = FLR_PREC_FP64;
+  o->preconditioner = FLR_PRECOND_AUTO;
+}
+
+const char* flr_status_string(flr_status st) {
+  switch (st) {
+    case FLR_OK: return "ok";
+    case FLR_ERR_INVALID_ARG: return "invalid argument";
+    case FLR_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case FLR_ERR_DEVICE: return "device error";
+    case FLR_ERR_NUMERICAL: return "numerical failure";
+    case FLR_ERR_MAX_ITER: return "iteration cap reached";
+    case FLR_ERR_BUSY: return "busy";
+    case FLR_ERR_NOT_READY: return "not ready";
+  }
+  return "unknown status";
+}
+
+const char* flr_last_error(void) { return g_last_error.c_str(); }
+
+flr_status flr_ctx_create(int device, void* hip_stream, flr_ctx* out) {
+  if (!out) return fail(FLR_ERR_INVALID_ARG, "out is NULL");
+  int ndev = 0;
+  HIP_OR_FAIL(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(FLR_ERR_INVALID_ARG, "no such device");
+  HIP_OR_FAIL(hipSetDevice(device));
+  flr_ctx c = new flr_ctx_s;
+  c->device = device;
+  if (hip_stream) {
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete c;
+      return fail(FLR_ERR_DEVICE, hipGetErrorString(e));
+    }
+    c->own_stream = true;
+  }
+  *out = c;
+  return FLR_OK;
+}
+
+void flr_ctx_destroy(flr_ctx c) {
+  if (!c) return;
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+static void problem_free(flr_problem h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  for (void* p : h->allocs) (void)hipFree(p);
+  if (h->h_prm) (void)hipHostFree(h->h_prm);
+  if (h->h_state) (void)hipHostFree(h->h_state);
+  for (auto& e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+}
+
+flr_status flr_create(flr_ctx ctx, const void* X, flr_dtype x_dtype, int64_t n, int64_t p, int64_t ldx,
+                      const double* y, const int64_t* edges, int64_t m, flr_problem* out) {
+  if (!ctx || !X || !y || !out) return fail(FLR_ERR_INVALID_ARG, "NULL argument");
+  if (n < 1 || p < 1 || ldx < p) return fail(FLR_ERR_INVALID_ARG, "need n >= 1, p >= 1, ldx >= p");
+  if (x_dtype != FLR_F64 && x_dtype != FLR_F32 && x_dtype != FLR_BF16)
+    return fail(FLR_ERR_INVALID_ARG, "unknown x_dtype");
+  if (m < 0 || (m > 0 && !edges)) return fail(FLR_ERR_INVALID_ARG, "bad edge list");
+  if (n > (int64_t)1 << 31 || p > (int64_t)kMaxBlocks * kBlk - 2048)
+    return fail(FLR_ERR_INVALID_ARG, "problem too large for this build (p <= 260000)");
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(y[i])) return fail(FLR_ERR_INVALID_ARG, "y has a non-finite value");
+  // canonical unordered edge set
+  std::vector<std::pair<int64_t, int64_t>> ev;
+  ev.reserve((size_t)m);
+  for (int64_t e = 0; e < m; ++e) {
+    int64_t j = edges[2 * e], k = edges[2 * e + 1];
+    if (j < 0 || k < 0 || j >= p || k >= p) return fail(FLR_ERR_INVALID_ARG, "edge index out of range");
+    if (j == k) return fail(FLR_ERR_INVALID_ARG, "self-loop in the edge set");
+    ev.emplace_back(std::min(j, k), std::max(j, k));
+  }
+  std::sort(ev.begin(), ev.end());
+  ev.erase(std::unique(ev.begin(), ev.end()), ev.end());
+  const int64_t mm = (int64_t)ev.size();
+  if (2 * mm > (int64_t)INT32_MAX) return fail(FLR_ERR_INVALID_ARG, "too many edges");
+  // symmetric CSR, columns sorted per row
+  std::vector<int32_t> deg((size_t)p + 1, 0);
+  for (auto& e : ev) {
+    deg[(size_t)e.first + 1]++;
+    deg[(size_t)e.second + 1]++;
+  }
+  std::vector<int32_t> rowptr((size_t)p + 1, 0);
+  for (int64_t j = 0; j < p; ++j) rowptr[(size_t)j + 1] = rowptr[(size_t)j] + deg[(size_t)j + 1];
+  std::vector<int32_t> col((size_t)std::max<int64_t>(2 * mm, 1)), fill(rowptr.begin(), rowptr.end() - 1);
+  for (auto& e : ev) {
+    col[(size_t)fill[(size_t)e.first]++] = (int32_t)e.second;
+    col[(size_t)fill[(size_t)e.second]++] = (int32_t)e.first;
+  }
+  std::vector<int32_t> prevpos((size_t)p, -1);
+  for (int64_t j = 0; j < p; ++j) {
+    std::sort(col.begin() + rowptr[(size_t)j], col.begin() + rowptr[(size_t)j + 1]);
+    for (int32_t q = rowptr[(size_t)j]; q < rowptr[(size_t)j + 1]; ++q)
+      if (col[(size_t)q] == j - 1) prevpos[(size_t)j] = q;
+  }
+
+  HIP_OR_FAIL(hipSetDevice(ctx->device));
+  flr_problem h = new flr_problem_s;
+  h->ctx = ctx;
+  h->m = mm;
+  h->nnz = 2 * mm;
+  h->D = choose_dims(n, p, x_dtype);
+  const Dims& D = h->D;
+  auto bail = [&](flr_status st) {
+    problem_free(h);
+    return st;
+  };
+#define CK(expr)                                                                                           \
+  do {                                                                                                     \
+    hipError_t e_ = (expr);                                                                                \
+    if (e_ != hipSuccess)                                                                                  \
+      return bail(fail(e_ == hipErrorOutOfMemory ? FLR_ERR_OUT_OF_MEMORY : FLR_ERR_DEVICE,                 \
+                       std::string(#expr) + ": " + hipGetErrorString(e_)));                                \
+  } while (0)
+  CK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+  CK(hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming));
+  CK(hipEventCreateWithFlags(&h->ev[1], hipEventDisableTiming));
+  CK(hipHostMalloc(reinterpret_cast<void**>(&h->h_prm), sizeof(Params), hipHostMallocDefault));
+  CK(hipHostMalloc(reinterpret_cast<void**>(&h->h_state), 2 * sizeof(State), hipHostMallocDefault));
+  const size_t xb = x_dtype == FLR_F64 ? 8 : x_dtype == FLR_F32 ? 4 : 2;
+  void* Xd = nullptr;
+  {
+    size_t bytes = (size_t)n * (size_t)D.ldx * xb;
+    CK(hipMalloc(&Xd, bytes));
+    h->allocs.push_back(Xd);
+    h->footprint += bytes;
+    CK(hipMemsetAsync(Xd, 0, bytes, h->stream));
+    CK(hipMemcpy2DAsync(Xd, (size_t)D.ldx * xb, X, (size_t)ldx * xb, (size_t)p * xb, (size_t)n, hipMemcpyDefault,
+                        h->stream));
+  }
+  Bufs& B = h->B;
+  B.X = Xd;
+  double *yd, *c, *s, *cpart, *spart;
+  int32_t *rp, *cl, *pp;
+  int* flag;
+  CK(dalloc(h, &yd, (size_t)n));
+  CK(dalloc(h, &rp, (size_t)p + 1));
+  CK(dalloc(h, &cl, col.size()));
+  CK(dalloc(h, &pp, (size_t)p));
+  CK(dalloc(h, &c, (size_t)D.p_pad));
+  CK(dalloc(h, &s, (size_t)D.p_pad));
+  CK(dalloc(h, &B.x, (size_t)D.p_pad));
+  CK(dalloc(h, &B.r, (size_t)D.p_pad));
+  CK(dalloc(h, &B.yv, (size_t)D.p_pad));
+  CK(dalloc(h, &B.pbuf, 2 * (size_t)D.p_pad));
+  CK(dalloc(h, &B.a, (size_t)D.p_pad));
+  CK(dalloc(h, &B.w, col.size()));
+  CK(dalloc(h, &B.d, (size_t)D.p_pad));
+  CK(dalloc(h, &B.e, (size_t)D.p_pad));
+  CK(dalloc(h, &B.L, (size_t)D.p_pad));
+  CK(dalloc(h, &B.invD, (size_t)D.p_pad));
+  CK(dalloc(h, &B.sig, (size_t)D.p_pad));
+  CK(dalloc(h, &B.psi, (size_t)D.p_pad));
+  CK(dalloc(h, &B.upart, (size_t)D.cb1 * (size_t)n));
+  CK(dalloc(h, &B.qpart, (size_t)D.rb2 * (size_t)D.p_pad));
+  CK(dalloc(h, &B.pqpart, (size_t)D.gridB));
+  CK(dalloc(h, &B.losspart, (size_t)D.rb2));
+  CK(dalloc(h, &B.penpart, (size_t)D.nblk));
+  CK(dalloc(h, &B.blk, (size_t)BK_N * (size_t)D.nblk));
+  CK(dalloc(h, &B.mob, 4 * (size_t)D.nblk));
+  CK(dalloc(h, &B.st, 2));
+  CK(dalloc(h, &h->d_prm, 1));
+  CK(dalloc(h, &flag, 1));
+  B.y = yd;
+  B.rowptr = rp;
+  B.col = cl;
+  B.prevpos = pp;
+  B.c = c;
+  B.s = s;
+  B.prm = h->d_prm;
+  CK(hipMemcpyAsync(yd, y, (size_t)n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  CK(hipMemcpyAsync(rp, rowptr.data(), rowptr.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  CK(hipMemcpyAsync(cl, col.data(), col.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  CK(hipMemcpyAsync(pp, prevpos.data(), prevpos.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  CK(launch_check_finite(Xd, x_dtype, (int64_t)n * D.ldx, flag, h->stream));
+  // setup partials reuse the q/u work areas: qpart holds rb2 x p_pad doubles
+  cpart = B.qpart;
+  double* tmp2 = nullptr;
+  CK(hipMalloc(reinterpret_cast<void**>(&tmp2), (size_t)D.rb2 * (size_t)D.p_pad * sizeof(double)));
+  spart = tmp2;
+  CK(launch_setup(D, Xd, yd, cpart, spart, c, s, h->stream));
+  int hflag = 0;
+  CK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  std::vector<double> hc((size_t)D.p);
+  CK(hipMemcpyAsync(hc.data(), c, (size_t)D.p * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  CK(hipStreamSynchronize(h->stream));
+  (void)hipFree(tmp2);
+  if (hflag) return bail(fail(FLR_ERR_INVALID_ARG, "X has a non-finite value"));
+  double cn = 0.0;
+  for (double v : hc) cn += v * v;
+  h->cnorm = std::sqrt(cn);
+#undef CK
+  *out = h;
+  return FLR_OK;
+}
+
+void flr_destroy(flr_problem h) { problem_free(h); }
+
+flr_status flr_problem_footprint(flr_problem h, size_t* bytes) {
+  if (!h || !bytes) return fail(FLR_ERR_INVALID_ARG, "NULL argument");
+  *bytes = h->footprint;
+  return FLR_OK;
+}
+int64_t flr_problem_n(flr_problem h) { return h ? h->D.n : -1; }
+int64_t flr_problem_p(flr_problem h) { return h ? h->D.p : -1; }
+int64_t flr_problem_m(flr_problem h) { return h ? h->m : -1; }
+
+flr_status flr_solve_ex(flr_problem h, double l1, double l2, double tol, const flr_solve_opts* opts, double* beta_out,
+                        flr_result* res) {
+  if (!h) return fail(FLR_ERR_INVALID_ARG, "NULL problem");
+  flr_status v = validate_lambdas(l1, l2, tol);
+  if (v != FLR_OK) return v;
+  std::unique_lock<std::mutex> lk(h->busy, std::try_to_lock);
+  if (!lk.owns_lock()) return fail(FLR_ERR_BUSY, "problem handle in use by another thread");
+  if (hipSetDevice(h->ctx->device) != hipSuccess) return fail(FLR_ERR_DEVICE, "hipSetDevice failed");
+  return run_solve(h, l1, l2, tol, opts, beta_out, res);
+}
+
+flr_status flr_solve(flr_problem h, double l1, double l2, double tol, double* beta_out_host, double* objective_out,
+                     int32_t* iterations_out) {
+  if (!beta_out_host) return fail(FLR_ERR_INVALID_ARG, "beta_out is NULL");
+  flr_result r{};
+  flr_status st = flr_solve_ex(h, l1, l2, tol, nullptr, beta_out_host, &r);
+  if (st == FLR_OK || st == FLR_ERR_MAX_ITER || st == FLR_ERR_NUMERICAL) {
+    if (objective_out) *objective_out = r.objective;
+    if (iterations_out) *iterations_out = r.mm_iters;
+  }
+  return st;
+}
+
+flr_status flr_solve_grid(flr_problem h, const double* l1, const double* l2, int32_t B, double tol,
+                          const flr_solve_opts* opts, double* beta_out, flr_result* res) {
+  if (!h || !l1 || !l2 || B < 1) return fail(FLR_ERR_INVALID_ARG, "bad grid arguments");
+  for (int32_t i = 0; i < B; ++i) {
+    flr_status v = validate_lambdas(l1[i], l2[i], tol);
+    if (v != FLR_OK) return v;
+  }
+  flr_status first = FLR_OK;
+  const bool dev = beta_out && is_device_ptr(beta_out);
+  for (int32_t i = 0; i < B; ++i) {
+    double* out = beta_out ? beta_out + (size_t)i * (size_t)h->D.p : nullptr;
+    flr_result r{};
+    flr_status st = flr_solve_ex(h, l1[i], l2[i], tol, opts, out, &r);
+    (void)dev;
+    if (res) res[i] = r;
+    if (st != FLR_OK && first == FLR_OK) first = st;
+    if (st != FLR_OK && st != FLR_ERR_MAX_ITER && st != FLR_ERR_NUMERICAL) return st;
+  }
+  return first;
+}
+
+}  // extern "C"

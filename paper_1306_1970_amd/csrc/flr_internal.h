@@ -1,0 +1,92 @@
+// Internal layout shared by the HIP kernels and the host engine.
+//
+// One solve is a device-resident state machine.  Every launch is one of three
+// kernels that run in a fixed rotation A, B, C (a hipGraph holds S rounds):
+//   A  row-panel GEMV   u = X v            (v = new CG direction, or the MM iterate)
+//   B  column-panel GEMV q = X^T u (+ M v)  (plus, at an MM boundary: objective
+//                                            partials, reweighting, factorization products)
+//   C  per-block work   CG updates and the block-partitioned tridiagonal solve,
+//                       or, at an MM boundary: objective test, factorization, new residual
+// Each kernel reads the state written by the previous one and writes the next
+// (double-buffered by launch parity), so the host only launches and polls.
+#pragma once
+#include <stdint.h>
+
+namespace flr {
+
+constexpr int kWG = 256;          // threads per workgroup (4 wave64)
+constexpr int kBlk = 256;         // elements per solver block (one per thread)
+constexpr int kMaxC1 = 2048;      // max columns of an A tile
+constexpr int kMaxR2 = 1024;      // max rows of a B tile
+constexpr int kMaxBlocks = 1024;  // max solver blocks -> p_pad <= 262144
+
+enum Phase : int32_t { PH_CG = 0, PH_END = 1, PH_DONE = 2 };
+enum SolveStatus : int32_t { ST_OK = 0, ST_MAX_ITER = 1, ST_NUMERICAL = 2 };
+
+// Block scalars of the partitioned tridiagonal solve (index into blk[]).
+enum BlkField : int {
+  BK_A = 0,    // forward gain of the block: prod(-L_j)
+  BK_B = 1,    // zero-inflow forward value at the block end
+  BK_SIGS = 2, // sigma at the block start
+  BK_PSIS = 3, // psi at the block start
+  BK_YS = 4,   // zero-inflow local solution at the block start
+  BK_RY = 5,   // r . y over the block
+  BK_RS = 6,   // r . sigma
+  BK_RP = 7,   // r . psi
+  BK_RR = 8,   // r . r
+  BK_N = 9
+};
+
+struct Params {
+  double lam1, lam2, eps, tol, inner_tol, cnorm;
+  int32_t max_iter, max_cg, jacobi, mixed;
+};
+
+struct State {
+  int32_t phase, status, first, first_cg;
+  int32_t mm_iter, cg_iter;
+  int64_t cg_total;
+  double rz, f_old, f_new, rel_change, rel_res, nu;
+};
+
+struct Dims {
+  int64_t n, p, p_pad, ldx;
+  int32_t dtype;          // 0 f64, 1 f32, 2 bf16
+  int32_t c1, cb1, r1, rb1;
+  int32_t c2, cb2, r2, rb2;
+  int32_t nblk;
+  int32_t gridB;          // max(cb2*rb2, nblk)
+};
+
+struct Bufs {
+  const void* X;
+  const double* y;
+  const int32_t* rowptr;
+  const int32_t* col;
+  const int32_t* prevpos;
+  const double* c;
+  const double* s;
+  double* x;
+  double* r;
+  double* yv;
+  double* pbuf;     // 2 * p_pad
+  double* a;
+  double* w;        // 2m CSR weights
+  double* d;
+  double* e;
+  double* L;
+  double* invD;
+  double* sig;
+  double* psi;
+  double* upart;    // cb1 * n
+  double* qpart;    // rb2 * p_pad
+  double* pqpart;   // gridB
+  double* losspart; // rb2
+  double* penpart;  // nblk
+  double* blk;      // BK_N * nblk
+  double* mob;      // 4 * nblk
+  State* st;        // 2
+  const Params* prm;
+};
+
+}  // namespace flr

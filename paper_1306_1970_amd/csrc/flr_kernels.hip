@@ -1,0 +1,796 @@
+// HIP kernels (gfx950) of the device-resident MM / PCG loop for fused lasso
+// regression.  Method: section 3.1 (perturbed objective, majorizer, linear
+// system with A and B), Algorithm 2 (MM with PCG, preconditioner
+// M = lambda1 A + lambda2 B).  See flr_internal.h for the launch rotation.
+//
+// Numerics: all p-scale arithmetic, dot products, the objective and every
+// stopping test are FP64.  X is read in its stored type (f64 / f32 / bf16)
+// and widened exactly; products accumulate in FP64.  Every reduction has a
+// fixed tree, so a solve is bitwise repeatable and does not depend on what
+// else runs on the device.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "flr_internal.h"
+
+namespace flr {
+
+// ---------------------------------------------------------------------------
+// stored-type loads: 16 bytes per lane, widened to double
+// ---------------------------------------------------------------------------
+template <typename XT> struct XV;
+template <> struct XV<double> {
+  static constexpr int V = 2;
+  using raw = double2;
+  __device__ static inline void cvt(const raw& v, double* o) { o[0] = v.x; o[1] = v.y; }
+};
+template <> struct XV<float> {
+  static constexpr int V = 4;
+  using raw = float4;
+  __device__ static inline void cvt(const raw& v, double* o) {
+    o[0] = (double)v.x; o[1] = (double)v.y; o[2] = (double)v.z; o[3] = (double)v.w;
+  }
+};
+template <> struct XV<uint16_t> {  // bfloat16 bit patterns
+  static constexpr int V = 8;
+  using raw = uint4;
+  __device__ static inline double lo(uint32_t w) { return (double)__uint_as_float(w << 16); }
+  __device__ static inline double hi(uint32_t w) { return (double)__uint_as_float(w & 0xffff0000u); }
+  __device__ static inline void cvt(const raw& v, double* o) {
+    o[0] = lo(v.x); o[1] = hi(v.x); o[2] = lo(v.y); o[3] = hi(v.y);
+    o[4] = lo(v.z); o[5] = hi(v.z); o[6] = lo(v.w); o[7] = hi(v.w);
+  }
+};
+
+template <typename XT>
+__device__ inline typename XV<XT>::raw load16(const XT* p) {
+  return *reinterpret_cast<const typename XV<XT>::raw*>(p);
+}
+
+// ---------------------------------------------------------------------------
+// reductions and scans over one 256-thread workgroup (fixed trees)
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the workgroup; every thread receives the result.  lds: 4 doubles.
+__device__ inline double wg_sum(double v, double* lds) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) lds[w] = v;
+  __syncthreads();
+  return (lds[0] + lds[1]) + (lds[2] + lds[3]);
+}
+
+// Affine map t -> a t + b.  compose(E, L) applies E first, then L.
+struct Aff {
+  double a, b;
+};
+__device__ inline Aff compose(Aff E, Aff Lm) { return {Lm.a * E.a, Lm.a * E.b + Lm.b}; }
+
+// Inclusive scan in thread order 0..255 (recurrence t_j = a_j t_{j-1} + b_j).
+// lds: 8 doubles.
+__device__ inline Aff wg_scan_fwd(Aff m, double* lds) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    double pa = __shfl_up(m.a, d, 64), pb = __shfl_up(m.b, d, 64);
+    if (l >= d) m = compose({pa, pb}, m);
+  }
+  __syncthreads();
+  if (l == 63) { lds[2 * w] = m.a; lds[2 * w + 1] = m.b; }
+  __syncthreads();
+  Aff pre = {1.0, 0.0};
+  for (int v = 0; v < w; ++v) pre = compose(pre, {lds[2 * v], lds[2 * v + 1]});
+  return compose(pre, m);
+}
+
+// Inclusive scan in thread order 255..0 (recurrence t_j = a_j t_{j+1} + b_j).
+__device__ inline Aff wg_scan_rev(Aff m, double* lds) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    double pa = __shfl_down(m.a, d, 64), pb = __shfl_down(m.b, d, 64);
+    if (l + d < 64) m = compose({pa, pb}, m);
+  }
+  __syncthreads();
+  if (l == 0) { lds[2 * w] = m.a; lds[2 * w + 1] = m.b; }
+  __syncthreads();
+  Aff pre = {1.0, 0.0};
+  for (int v = 3; v > w; --v) pre = compose(pre, {lds[2 * v], lds[2 * v + 1]});
+  return compose(pre, m);
+}
+
+// 2x2 projective (Moebius) product used for the continued fraction
+// D_j = d_j - e_j^2 / D_{j-1} of the tridiagonal LDL^T factorization.
+struct Mob {
+  double m00, m01, m10, m11;
+};
+__device__ inline Mob mob_norm(Mob o) {
+  double mx = fmax(fmax(fabs(o.m00), fabs(o.m01)), fmax(fabs(o.m10), fabs(o.m11)));
+  if (mx > 0.0 && isfinite(mx)) {
+    int ex = ilogb(mx);
+    o.m00 = ldexp(o.m00, -ex); o.m01 = ldexp(o.m01, -ex);
+    o.m10 = ldexp(o.m10, -ex); o.m11 = ldexp(o.m11, -ex);
+  }
+  return o;
+}
+// L * R (R acts first)
+__device__ inline Mob mob_mul(Mob Lm, Mob R) {
+  return mob_norm({Lm.m00 * R.m00 + Lm.m01 * R.m10, Lm.m00 * R.m01 + Lm.m01 * R.m11,
+                   Lm.m10 * R.m00 + Lm.m11 * R.m10, Lm.m10 * R.m01 + Lm.m11 * R.m11});
+}
+
+__device__ inline void copy_state(const State* sin, State* sout, const State& s) {
+  (void)sin;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *sout = s;
+}
+
+// ---------------------------------------------------------------------------
+// Setup: partial column sums of X_ij y_i and X_ij^2 over row panels
+// ---------------------------------------------------------------------------
+template <typename XT>
+__global__ __launch_bounds__(kWG) void k_setup_partial(Dims D, const XT* __restrict__ X, const double* __restrict__ y,
+                                                        double* __restrict__ cpart, double* __restrict__ spart) {
+  constexpr int V = XV<XT>::V;
+  const int wg = blockIdx.x, cb = wg % D.cb2, rb = wg / D.cb2;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t r0 = (int64_t)rb * D.r2, r1 = min<int64_t>(D.n, r0 + D.r2);
+  const int64_t c0 = (int64_t)cb * D.c2 + lane * V;
+  double ac[V], as[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) { ac[v] = 0.0; as[v] = 0.0; }
+  for (int64_t i = r0 + wave; i < r1; i += 4) {
+    double xv[V];
+    XV<XT>::cvt(load16(X + i * D.ldx + c0), xv);
+    const double yi = y[i];
+#pragma unroll
+    for (int v = 0; v < V; ++v) { ac[v] = fma(xv[v], yi, ac[v]); as[v] = fma(xv[v], xv[v], as[v]); }
+  }
+  __shared__ double red[2][4][64 * 8];
+#pragma unroll
+  for (int v = 0; v < V; ++v) { red[0][wave][lane * V + v] = ac[v]; red[1][wave][lane * V + v] = as[v]; }
+  __syncthreads();
+  for (int t = threadIdx.x; t < 64 * V; t += kWG) {
+    const int64_t j = (int64_t)cb * D.c2 + t;
+    cpart[(int64_t)rb * D.p_pad + j] = (red[0][0][t] + red[0][1][t]) + (red[0][2][t] + red[0][3][t]);
+    spart[(int64_t)rb * D.p_pad + j] = (red[1][0][t] + red[1][1][t]) + (red[1][2][t] + red[1][3][t]);
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_setup_final(Dims D, const double* __restrict__ cpart,
+                                                      const double* __restrict__ spart, double* __restrict__ c,
+                                                      double* __restrict__ s) {
+  const int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (j >= D.p_pad) return;
+  double sc = 0.0, ss = 0.0;
+  for (int rb = 0; rb < D.rb2; ++rb) {
+    sc += cpart[(int64_t)rb * D.p_pad + j];
+    ss += spart[(int64_t)rb * D.p_pad + j];
+  }
+  c[j] = j < D.p ? sc : 0.0;
+  s[j] = j < D.p ? ss : 0.0;
+}
+
+// Initial iterate (initialization of Algorithms 1 and 2: b_j = X_j^T y / X_j^T X_j,
+// 0 for a zero column) or a warm start; both state buffers start at the MM
+// boundary so the first rotation evaluates f(b0) and sets up the first PCG.
+__global__ __launch_bounds__(kWG) void k_init(Dims D, Bufs B, const double* __restrict__ warm, int use_warm) {
+  const int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (j < D.p_pad) {
+    double v = 0.0;
+    if (j < D.p) v = use_warm ? warm[j] : (B.s[j] > 0.0 ? B.c[j] / B.s[j] : 0.0);
+    B.x[j] = v;
+    B.r[j] = 0.0;
+    B.yv[j] = 0.0;
+    B.pbuf[j] = 0.0;
+    B.pbuf[D.p_pad + j] = 0.0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    State s;
+    s.phase = PH_END;
+    s.status = ST_OK;
+    s.first = 1;
+    s.first_cg = 1;
+    s.mm_iter = 0;
+    s.cg_iter = 0;
+    s.cg_total = 0;
+    s.rz = 0.0;
+    s.f_old = 0.0;
+    s.f_new = 0.0;
+    s.rel_change = 0.0;
+    s.rel_res = 0.0;
+    s.nu = 0.0;
+    B.st[0] = s;
+    B.st[1] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A: row-panel GEMV.  In a PCG step it first rebuilds the preconditioned
+// residual z = M^-1 r from the block-partitioned solve (carries over blocks),
+// forms r^T z and ||r||, applies the inner stopping test of Algorithm 2 and
+// the direction update p = z + gamma p; then u_part[cb] = X[:, cb] p[cb].
+// When PCG has converged (or at the MM boundary) it multiplies the iterate x.
+// ---------------------------------------------------------------------------
+template <typename XT>
+__global__ __launch_bounds__(kWG) void k_gemv_a(Dims D, Bufs B, int par) {
+  constexpr int V = XV<XT>::V;
+  constexpr int NV = 4;  // 16-byte loads per lane per row
+  const State* sin = B.st + par;
+  State* sout = B.st + (par ^ 1);
+  const State s = *sin;
+  if (s.phase == PH_DONE) { copy_state(sin, sout, s); return; }
+  const Params prm = *B.prm;
+
+  __shared__ double sh_v[kMaxC1];
+  __shared__ double sh_G[kMaxBlocks];
+  __shared__ double sh_Z[kMaxBlocks];
+  __shared__ double sh_m[4];
+
+  const int wg = blockIdx.x, cb = wg % D.cb1, rb = wg / D.cb1;
+  const int tid = threadIdx.x;
+  bool use_x = true;
+  double gamma = 0.0;
+  const double* pold = B.pbuf + (int64_t)(s.cg_iter & 1) * D.p_pad;
+  double* pnew = B.pbuf + (int64_t)((s.cg_iter + 1) & 1) * D.p_pad;
+
+  if (s.phase == PH_CG) {
+    if (tid == 0) {
+      // carries of the partitioned tridiagonal solve: forward G_k (value of the
+      // forward sweep entering block k), backward Z_k (solution entering from the right)
+      const int K = D.nblk;
+      const double* bk = B.blk;
+      double G = 0.0;
+      sh_G[0] = 0.0;
+      for (int k = 1; k < K; ++k) {
+        G = fma(bk[BK_A * K + k - 1], G, bk[BK_B * K + k - 1]);
+        sh_G[k] = G;
+      }
+      double Z = 0.0;
+      sh_Z[K - 1] = 0.0;
+      for (int k = K - 2; k >= 0; --k) {
+        Z = bk[BK_YS * K + k + 1] + bk[BK_SIGS * K + k + 1] * sh_G[k + 1] + bk[BK_PSIS * K + k + 1] * Z;
+        sh_Z[k] = Z;
+      }
+      double rz = 0.0, rr = 0.0;
+      for (int k = 0; k < K; ++k) {
+        rz += bk[BK_RY * K + k] + sh_G[k] * bk[BK_RS * K + k] + sh_Z[k] * bk[BK_RP * K + k];
+        rr += bk[BK_RR * K + k];
+      }
+      sh_m[0] = rz;
+      sh_m[1] = rr;
+    }
+    __syncthreads();
+    const double rz = sh_m[0];
+    const double rn = sqrt(sh_m[1]) / prm.cnorm;
+    const bool done = !(rn > prm.inner_tol) || s.cg_iter >= prm.max_cg;
+    use_x = done;
+    if (!done) gamma = s.first_cg ? 0.0 : rz / s.rz;
+    if (wg == 0 && tid == 0) {
+      State o = s;
+      o.rel_res = rn;
+      if (done) {
+        o.phase = PH_END;
+      } else {
+        o.rz = rz;
+        o.first_cg = 0;
+      }
+      *sout = o;
+    }
+  } else {
+    copy_state(sin, sout, s);
+  }
+
+  // operand slice of this column panel
+  const int64_t c0 = (int64_t)cb * D.c1;
+  for (int t = tid; t < D.c1; t += kWG) {
+    const int64_t j = c0 + t;
+    double v;
+    if (use_x) {
+      v = B.x[j];
+    } else {
+      const int k = (int)(j / kBlk);
+      const double z = B.yv[j] + B.sig[j] * sh_G[k] + B.psi[j] * sh_Z[k];
+      v = fma(gamma, pold[j], z);
+      if (rb == 0) pnew[j] = v;
+    }
+    sh_v[t] = v;
+  }
+  __syncthreads();
+
+  // u_part[cb][i] = sum_j X_ij v_j over the panel, rows r0..r1
+  const int lane = tid & 63, wave = tid >> 6;
+  const int64_t r0 = (int64_t)rb * D.r1, r1 = min<int64_t>(D.n, r0 + D.r1);
+  const int nv = D.c1 / (64 * V);  // loads per lane per row (<= NV)
+  double pl[NV][V];
+#pragma unroll
+  for (int t = 0; t < NV; ++t)
+#pragma unroll
+    for (int v = 0; v < V; ++v) pl[t][v] = (t < nv) ? sh_v[(t * 64 + lane) * V + v] : 0.0;
+  const XT* Xb = reinterpret_cast<const XT*>(B.X);
+  for (int64_t i = r0 + wave; i < r1; i += 4 * 2) {
+    double acc0 = 0.0, acc1 = 0.0;
+    const int64_t i1 = i + 4;
+    const bool has1 = i1 < r1;
+#pragma unroll
+    for (int t = 0; t < NV; ++t) {
+      if (t < nv) {
+        const int64_t col = c0 + (int64_t)(t * 64 + lane) * V;
+        double xv[V];
+        XV<XT>::cvt(load16(Xb + i * D.ldx + col), xv);
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc0 = fma(xv[v], pl[t][v], acc0);
+        if (has1) {
+          double xw[V];
+          XV<XT>::cvt(load16(Xb + i1 * D.ldx + col), xw);
+#pragma unroll
+          for (int v = 0; v < V; ++v) acc1 = fma(xw[v], pl[t][v], acc1);
+        }
+      }
+    }
+    acc0 = wave_sum(acc0);
+    acc1 = wave_sum(acc1);
+    if (lane == 0) {
+      B.upart[(int64_t)cb * D.n + i] = acc0;
+      if (has1) B.upart[(int64_t)cb * D.n + i1] = acc1;
+    }
+  }
+}
+
+// (M v)_j = lambda1 a_j v_j + lambda2 sum_k w_jk (v_j - v_k)  (A and B of the linear system)
+__device__ inline double apply_m(const Bufs& B, const Params& prm, int64_t j, const double* v) {
+  const double vj = v[j];
+  double lap = 0.0;
+  for (int q = B.rowptr[j]; q < B.rowptr[j + 1]; ++q) lap = fma(B.w[q], vj - v[B.col[q]], lap);
+  return prm.lam1 * B.a[j] * vj + prm.lam2 * lap;
+}
+
+// ---------------------------------------------------------------------------
+// B: column-panel GEMV q_part[rb] = X[rb, :]^T u[rb] (u summed from the A
+// partials).  PCG step: panel row 0 adds M p and each workgroup emits its
+// share of p^T Q p.  MM boundary: the same product for the new residual, the
+// loss partials 1/2 ||y - X b||^2, and (first nblk workgroups) reweighting
+// a_j = 1/(|b_j|+eps), w_jk = 1/(|b_j - b_k|+eps), the tridiagonal part of M,
+// the penalty sums of f, and each block's factorization product.
+// ---------------------------------------------------------------------------
+template <typename XT>
+__global__ __launch_bounds__(kWG) void k_gemv_b(Dims D, Bufs B, int par) {
+  constexpr int V = XV<XT>::V;
+  const State* sin = B.st + par;
+  State* sout = B.st + (par ^ 1);
+  const State s = *sin;
+  copy_state(sin, sout, s);
+  if (s.phase == PH_DONE) return;
+  const Params prm = *B.prm;
+  const bool cg = s.phase == PH_CG;
+  const double* pv = cg ? (B.pbuf + (int64_t)((s.cg_iter + 1) & 1) * D.p_pad) : B.x;
+
+  __shared__ double sh_u[kMaxR2];
+  __shared__ double sh_red[4][64 * 8];
+  __shared__ double sh_s[4];
+  __shared__ double sh_d[kBlk], sh_e[kBlk];
+
+  const int wg = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int ngemm = D.cb2 * D.rb2;
+  if (wg < ngemm) {
+    const int cb = wg % D.cb2, rb = wg / D.cb2;
+    const int64_t r0 = (int64_t)rb * D.r2, r1 = min<int64_t>(D.n, r0 + D.r2);
+    const int nr = (int)(r1 - r0);
+    double loss = 0.0;
+    for (int t = tid; t < nr; t += kWG) {
+      double u = 0.0;
+      for (int q = 0; q < D.cb1; ++q) u += B.upart[(int64_t)q * D.n + r0 + t];
+      sh_u[t] = u;
+      if (!cg && cb == 0) {
+        const double dlt = B.y[r0 + t] - u;
+        loss = fma(dlt, dlt, loss);
+      }
+    }
+    __syncthreads();
+    const int64_t c0 = (int64_t)cb * D.c2 + lane * V;
+    double acc[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[v] = 0.0;
+    const XT* Xb = reinterpret_cast<const XT*>(B.X);
+    int64_t i = r0 + wave;
+    for (; i + 12 < r1; i += 16) {
+      double x0[V], x1[V], x2[V], x3[V];
+      XV<XT>::cvt(load16(Xb + i * D.ldx + c0), x0);
+      XV<XT>::cvt(load16(Xb + (i + 4) * D.ldx + c0), x1);
+      XV<XT>::cvt(load16(Xb + (i + 8) * D.ldx + c0), x2);
+      XV<XT>::cvt(load16(Xb + (i + 12) * D.ldx + c0), x3);
+      const double u0 = sh_u[i - r0], u1 = sh_u[i + 4 - r0], u2 = sh_u[i + 8 - r0], u3 = sh_u[i + 12 - r0];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        acc[v] = fma(x0[v], u0, acc[v]);
+        acc[v] = fma(x1[v], u1, acc[v]);
+        acc[v] = fma(x2[v], u2, acc[v]);
+        acc[v] = fma(x3[v], u3, acc[v]);
+      }
+    }
+    for (; i < r1; i += 4) {
+      double x0[V];
+      XV<XT>::cvt(load16(Xb + i * D.ldx + c0), x0);
+      const double u0 = sh_u[i - r0];
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[v] = fma(x0[v], u0, acc[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) sh_red[wave][lane * V + v] = acc[v];
+    __syncthreads();
+    double dotp = 0.0;
+    for (int t = tid; t < 64 * V; t += kWG) {
+      const int64_t j = (int64_t)cb * D.c2 + t;
+      double q = (sh_red[0][t] + sh_red[1][t]) + (sh_red[2][t] + sh_red[3][t]);
+      if (cg && rb == 0 && j < D.p) q += apply_m(B, prm, j, pv);
+      B.qpart[(int64_t)rb * D.p_pad + j] = q;
+      if (cg) dotp = fma(pv[j], q, dotp);
+    }
+    if (cg) {
+      const double tot = wg_sum(dotp, sh_s);
+      if (tid == 0) B.pqpart[wg] = tot;
+    } else if (cb == 0) {
+      const double tot = wg_sum(loss, sh_s);
+      if (tid == 0) B.losspart[rb] = tot;
+    }
+  } else if (cg) {
+    if (tid == 0) B.pqpart[wg] = 0.0;
+  }
+
+  if (!cg && wg < D.nblk) {
+    // reweighting, tridiagonal part of M, penalties, block product
+    const int64_t j = (int64_t)wg * kBlk + tid;
+    double pen = 0.0, dj = 1.0, ej = 0.0;
+    if (j < D.p) {
+      const double xj = B.x[j];
+      const double aj = 1.0 / (fabs(xj) + prm.eps);
+      B.a[j] = aj;
+      double wsum = 0.0;
+      double pen2 = 0.0;
+      for (int q = B.rowptr[j]; q < B.rowptr[j + 1]; ++q) {
+        const int k = B.col[q];
+        const double dlt = fabs(xj - B.x[k]);
+        const double wq = 1.0 / (dlt + prm.eps);
+        B.w[q] = wq;
+        wsum += wq;
+        if (k > j) pen2 += dlt;
+      }
+      pen = prm.lam1 * fabs(xj) + prm.lam2 * pen2;
+      dj = prm.lam1 * aj + prm.lam2 * wsum;
+      if (prm.jacobi) {
+        dj += B.s[j];
+      } else if (B.prevpos[j] >= 0) {
+        // edge (j-1, j): its weight was computed for row j above (same |b_j - b_k| both ways)
+        ej = -prm.lam2 * (1.0 / (fabs(xj - B.x[j - 1]) + prm.eps));
+      }
+      B.d[j] = dj;
+      B.e[j] = ej;
+    } else if (j < D.p_pad) {
+      B.d[j] = 1.0;
+      B.e[j] = 0.0;
+    }
+    sh_d[tid] = dj;
+    sh_e[tid] = ej;
+    const double tot = wg_sum(pen, sh_s);
+    if (tid == 0) {
+      B.penpart[wg] = tot;
+      Mob T = {1.0, 0.0, 0.0, 1.0};
+      for (int t = 0; t < kBlk; ++t) {
+        if ((int64_t)wg * kBlk + t >= D.p) break;
+        const double et = sh_e[t];
+        T = mob_mul({sh_d[t], -et * et, 1.0, 0.0}, T);
+      }
+      B.mob[4 * wg + 0] = T.m00;
+      B.mob[4 * wg + 1] = T.m01;
+      B.mob[4 * wg + 2] = T.m10;
+      B.mob[4 * wg + 3] = T.m11;
+    }
+  }
+}
+
+// Zero-inflow local solve of the block for the current residual r_j and the
+// block scalars that the next A launch combines into the global solution:
+//   forward  g_j = r_j - L_j g_{j-1}         (L D L^T, forward sweep)
+//   backward y_j = g_j / D_j - L_{j+1} y_{j+1} (backward sweep)
+__device__ inline void block_local_solve(const Dims& D, const Bufs& B, int b, int64_t j, double rj, double Lj,
+                                         double Lnext, double invDj, double sigj, double psij, double* lds,
+                                         double* lds2) {
+  const int tid = threadIdx.x;
+  const Aff gf = wg_scan_fwd({-Lj, rj}, lds);
+  const double g = gf.b;
+  const Aff yb = wg_scan_rev({-Lnext, g * invDj}, lds);
+  const double yj = yb.b;
+  if (j < D.p_pad) B.yv[j] = yj;
+  const int K = D.nblk;
+  __syncthreads();
+  if (tid == kBlk - 1) lds2[0] = g;
+  if (tid == 0) lds2[1] = yj;
+  const double ry = wg_sum(rj * yj, lds);
+  const double rs = wg_sum(rj * sigj, lds);
+  const double rp = wg_sum(rj * psij, lds);
+  const double rr = wg_sum(rj * rj, lds);
+  if (tid == 0) {
+    B.blk[BK_B * K + b] = lds2[0];
+    B.blk[BK_YS * K + b] = lds2[1];
+    B.blk[BK_RY * K + b] = ry;
+    B.blk[BK_RS * K + b] = rs;
+    B.blk[BK_RP * K + b] = rp;
+    B.blk[BK_RR * K + b] = rr;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// C: per solver block (256 elements).  PCG step: nu = r^T z / p^T Q p,
+// x += nu p, r -= nu Q p (the residual update with the minus sign), then the
+// local solve of the new residual.  MM boundary: f of the iterate, the
+// relative-change test of Algorithm 2, and - if continuing - the LDL^T
+// factorization of the tridiagonal M (carry of the block products, then the
+// block's own continued fraction), the gain vectors, r0 = c - Q x0 and its
+// local solve.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_block(Dims D, Bufs B, int par) {
+  const State* sin = B.st + par;
+  State* sout = B.st + (par ^ 1);
+  const State s = *sin;
+  if (s.phase == PH_DONE) { copy_state(sin, sout, s); return; }
+  const Params prm = *B.prm;
+  __shared__ double lds[16];
+  __shared__ double lds2[4];
+  __shared__ double sh_D[kBlk];
+  __shared__ double sh_L[kBlk + 1];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  const int64_t j = (int64_t)b * kBlk + tid;
+  const bool real = j < D.p;
+  const int ngemm = D.cb2 * D.rb2;
+
+  if (s.phase == PH_CG) {
+    // p^T Q p from the B partials (fixed order)
+    double part = 0.0;
+    for (int q = tid; q < D.gridB; q += kWG) part += B.pqpart[q];
+    const double pq = wg_sum(part, lds);
+    const double nu = s.rz / pq;
+    if (!(pq > 0.0) || !isfinite(nu)) {
+      if (b == 0 && tid == 0) {
+        State o = s;
+        o.phase = PH_DONE;
+        o.status = ST_NUMERICAL;
+        *sout = o;
+      }
+      return;
+    }
+    const double* pv = B.pbuf + (int64_t)((s.cg_iter + 1) & 1) * D.p_pad;
+    double rj = 0.0, Lj = 0.0, invDj = 0.0, sigj = 0.0, psij = 0.0;
+    if (real) {
+      double q = 0.0;
+      for (int rb = 0; rb < D.rb2; ++rb) q += B.qpart[(int64_t)rb * D.p_pad + j];
+      B.x[j] = fma(nu, pv[j], B.x[j]);
+      rj = fma(-nu, q, B.r[j]);
+      B.r[j] = rj;
+      Lj = B.L[j];
+      invDj = B.invD[j];
+      sigj = B.sig[j];
+      psij = B.psi[j];
+    }
+    sh_L[tid] = Lj;
+    if (tid == 0) sh_L[kBlk] = (j + kBlk < D.p) ? B.L[j + kBlk] : 0.0;
+    __syncthreads();
+    block_local_solve(D, B, b, j, rj, Lj, sh_L[tid + 1], invDj, sigj, psij, lds, lds2);
+    if (b == 0 && tid == 0) {
+      State o = s;
+      o.cg_iter = s.cg_iter + 1;
+      o.cg_total = s.cg_total + 1;
+      o.nu = nu;
+      *sout = o;
+    }
+    return;
+  }
+
+  // ---- MM boundary ----
+  // f(b) = loss + penalties (identical arithmetic in every workgroup)
+  double fpart = 0.0;
+  for (int q = tid; q < D.rb2; q += kWG) fpart += B.losspart[q];
+  const double loss = wg_sum(fpart, lds);
+  double ppart = 0.0;
+  for (int q = tid; q < D.nblk; q += kWG) ppart += B.penpart[q];
+  const double pen = wg_sum(ppart, lds);
+  const double f_new = 0.5 * loss + pen;
+  State o = s;
+  o.f_new = f_new;
+  bool finish = false;
+  if (!isfinite(f_new)) {
+    o.status = ST_NUMERICAL;
+    finish = true;
+  } else if (s.first) {
+    o.first = 0;
+  } else {
+    o.mm_iter = s.mm_iter + 1;
+    const double re = s.f_old != 0.0 ? fabs(f_new - s.f_old) / fabs(s.f_old) : fabs(f_new - s.f_old);
+    o.rel_change = re;
+    if (re <= prm.tol) {
+      o.status = ST_OK;
+      finish = true;
+    } else if (o.mm_iter >= prm.max_iter) {
+      o.status = ST_MAX_ITER;
+      finish = true;
+    }
+  }
+  if (finish) {
+    o.phase = PH_DONE;
+    if (b == 0 && tid == 0) *sout = o;
+    return;
+  }
+  o.f_old = f_new;
+  o.phase = PH_CG;
+  o.first_cg = 1;
+  o.cg_iter = 0;
+
+  // factorization: D entering this block from the product of the previous blocks
+  if (tid == 0) {
+    double Din = INFINITY;
+    if (b > 0) {
+      double va = 1.0, vb = 0.0;
+      for (int k = 0; k < b; ++k) {
+        const double m00 = B.mob[4 * k], m01 = B.mob[4 * k + 1], m10 = B.mob[4 * k + 2], m11 = B.mob[4 * k + 3];
+        double na = m00 * va + m01 * vb, nb = m10 * va + m11 * vb;
+        double mx = fmax(fabs(na), fabs(nb));
+        if (mx > 0.0 && isfinite(mx)) {
+          const int ex = ilogb(mx);
+          na = ldexp(na, -ex);
+          nb = ldexp(nb, -ex);
+        }
+        va = na;
+        vb = nb;
+      }
+      Din = va / vb;
+    }
+    double Dp = Din;
+    for (int t = 0; t < kBlk; ++t) {
+      const int64_t jj = (int64_t)b * kBlk + t;
+      if (jj >= D.p) { sh_D[t] = 1.0; continue; }
+      const double et = B.e[jj];
+      const double Dj = et != 0.0 ? B.d[jj] - et * (et / Dp) : B.d[jj];
+      sh_D[t] = Dj;
+      Dp = Dj;
+    }
+    lds2[2] = Din;
+  }
+  __syncthreads();
+  double Lj = 0.0, invDj = 0.0;
+  if (real) {
+    const double ej = B.e[j];
+    const double Dm1 = tid == 0 ? lds2[2] : sh_D[tid - 1];
+    Lj = ej != 0.0 ? ej / Dm1 : 0.0;
+    invDj = 1.0 / sh_D[tid];
+  }
+  sh_L[tid] = Lj;
+  if (tid == kBlk - 1) {
+    const int64_t jn = j + 1;
+    double Ln = 0.0;
+    if (real && jn < D.p) {
+      const double en = B.e[jn];
+      Ln = en != 0.0 ? en / sh_D[tid] : 0.0;
+    }
+    sh_L[kBlk] = Ln;
+  }
+  __syncthreads();
+  const double Lnext = sh_L[tid + 1];
+  // phi_j = prod_{i=start..j} (-L_i); psi_j = prod_{i=j+1..end+1} (-L_i);
+  // sigma = zero-inflow backward sweep of phi / D
+  const double phi = wg_scan_fwd({-Lj, 0.0}, lds).a;
+  const double psi = wg_scan_rev({-Lnext, 0.0}, lds).a;
+  const double sig = wg_scan_rev({-Lnext, phi * invDj}, lds).b;
+  const double psij = real ? psi : 0.0;
+  const double sigj = real ? sig : 0.0;
+  if (j < D.p_pad) {
+    B.L[j] = Lj;
+    B.invD[j] = invDj;
+    B.sig[j] = sigj;
+    B.psi[j] = psij;
+  }
+  __syncthreads();
+  if (tid == kBlk - 1) lds2[0] = phi;
+  if (tid == 0) { lds2[1] = sigj; lds2[3] = psij; }
+  __syncthreads();
+  if (tid == 0) {
+    const int K = D.nblk;
+    B.blk[BK_A * K + b] = lds2[0];
+    B.blk[BK_SIGS * K + b] = lds2[1];
+    B.blk[BK_PSIS * K + b] = lds2[3];
+  }
+  // r0 = c - (X^T X + M) x0 with x0 the MM iterate (Algorithm 2)
+  double rj = 0.0;
+  if (real) {
+    double q = 0.0;
+    for (int rb = 0; rb < D.rb2; ++rb) q += B.qpart[(int64_t)rb * D.p_pad + j];
+    rj = B.c[j] - (q + apply_m(B, prm, j, B.x));
+    B.r[j] = rj;
+  }
+  (void)ngemm;
+  block_local_solve(D, B, b, j, rj, Lj, Lnext, invDj, sigj, psij, lds, lds2);
+  if (b == 0 && tid == 0) *sout = o;
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+template <typename XT>
+static hipError_t launch_rotation_t(const Dims& D, const Bufs& B, int par, int which, hipStream_t st) {
+  switch (which) {
+    case 0:
+      hipLaunchKernelGGL(k_gemv_a<XT>, dim3(D.cb1 * D.rb1), dim3(kWG), 0, st, D, B, par);
+      break;
+    case 1:
+      hipLaunchKernelGGL(k_gemv_b<XT>, dim3(D.gridB), dim3(kWG), 0, st, D, B, par);
+      break;
+    default:
+      hipLaunchKernelGGL(k_block, dim3(D.nblk), dim3(kWG), 0, st, D, B, par);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_rotation(const Dims& D, const Bufs& B, int par, int which, hipStream_t st) {
+  switch (D.dtype) {
+    case 0: return launch_rotation_t<double>(D, B, par, which, st);
+    case 1: return launch_rotation_t<float>(D, B, par, which, st);
+    default: return launch_rotation_t<uint16_t>(D, B, par, which, st);
+  }
+}
+
+template <typename XT>
+static hipError_t launch_setup_t(const Dims& D, const void* X, const double* y, double* cpart, double* spart,
+                                 double* c, double* s, hipStream_t st) {
+  hipLaunchKernelGGL(k_setup_partial<XT>, dim3(D.cb2 * D.rb2), dim3(kWG), 0, st, D, reinterpret_cast<const XT*>(X),
+                     y, cpart, spart);
+  hipLaunchKernelGGL(k_setup_final, dim3((unsigned)((D.p_pad + kWG - 1) / kWG)), dim3(kWG), 0, st, D, cpart, spart,
+                     c, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_setup(const Dims& D, const void* X, const double* y, double* cpart, double* spart, double* c,
+                        double* s, hipStream_t st) {
+  switch (D.dtype) {
+    case 0: return launch_setup_t<double>(D, X, y, cpart, spart, c, s, st);
+    case 1: return launch_setup_t<float>(D, X, y, cpart, spart, c, s, st);
+    default: return launch_setup_t<uint16_t>(D, X, y, cpart, spart, c, s, st);
+  }
+}
+
+hipError_t launch_init(const Dims& D, const Bufs& B, const double* warm, int use_warm, hipStream_t st) {
+  hipLaunchKernelGGL(k_init, dim3((unsigned)((D.p_pad + kWG - 1) / kWG)), dim3(kWG), 0, st, D, B, warm, use_warm);
+  return hipGetLastError();
+}
+
+// Non-finite scan of the stored X (validation at creation).
+template <typename XT>
+__global__ __launch_bounds__(kWG) void k_check_finite(const XT* __restrict__ X, int64_t count, int* flag) {
+  const int64_t stride = (int64_t)gridDim.x * kWG;
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < count; i += stride) {
+    if constexpr (sizeof(XT) == 2) {
+      bad |= (X[i] & 0x7f80u) == 0x7f80u;
+    } else {
+      bad |= !isfinite((double)X[i]);
+    }
+  }
+  if (bad) *flag = 1;
+}
+
+hipError_t launch_check_finite(const void* X, int dtype, int64_t count, int* flag, hipStream_t st) {
+  const dim3 g(1024), b(kWG);
+  switch (dtype) {
+    case 0: hipLaunchKernelGGL(k_check_finite<double>, g, b, 0, st, reinterpret_cast<const double*>(X), count, flag); break;
+    case 1: hipLaunchKernelGGL(k_check_finite<float>, g, b, 0, st, reinterpret_cast<const float*>(X), count, flag); break;
+    default: hipLaunchKernelGGL(k_check_finite<uint16_t>, g, b, 0, st, reinterpret_cast<const uint16_t*>(X), count, flag); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace flr
