@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Benchmark of the MM / PCG fused-lasso solver on one MI355X.
+
+One step = one complete solve (every MM iteration: reweighting, the
+tridiagonal factorization, the PCG inner loop with its X / X^T products,
+Laplacian and preconditioner, the FP64 objective test) of the headline
+workload with X, y and the edge set already resident in HBM.  Prints one
+JSON line.
+
+Workloads (--workload):
+  c2  standard FLR, chain, n=1000, p=10000, X FP32 with AR(1) rho=0.5 rows,
+      beta 50 blocks 80% zero, sigma=0.5, (lambda1, lambda2)=(0.5, 1.0), tol 1e-8
+      (the configuration the headline metric is quoted on; default)
+  c1  n=100, p=500, FP64 X (small case)
+  c4  n=5000, p=50000, X stored BF16, y FP32
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FLR solves/sec at p=10k + HBM GB/s; batched/mixed vs plain at 1e-6 obj gap"
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("flr_kernels.hip", "flr_internal.h"):
+        with open(os.path.join(ROOT, "paper_1306_1970_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def make_workload(name):
+    import flrgen
+
+    if name == "c1":
+        return flrgen.config1(), "c1_chain_n100_p500_f64"
+    if name == "c4":
+        return flrgen.config4(), "c4_chain_n5000_p50000_bf16"
+    return flrgen.config2(), "c2_chain_ar1_n1000_p10000_f32"
+
+
+def cpu_baseline(inst, gpu_cg_total: int, mm_sample: int):
+    """The FP64 oracle (Algorithm 2, as it stands) on a bounded sample of the
+    same solve: the first mm_sample MM iterations.  Extrapolated to a full
+    solve by the PCG step count of the GPU solve of the same instance."""
+    import oracle
+
+    P = oracle.Problem.from_instance(inst)
+    t0 = time.perf_counter()
+    r = oracle.solve(P, inst.lam1, inst.lam2, eps=inst.eps, tol=inst.tol, max_iter=mm_sample, method=oracle.ALG2)
+    dt = time.perf_counter() - t0
+    cg = max(1, r.cg_iters)
+    sec_per_solve = dt / cg * max(gpu_cg_total, 1)
+    return {
+        "value": 1.0 / sec_per_solve,
+        "unit": "solves/s",
+        "cores": int(r.threads),
+        "kind": "oracle",
+        "sample": "first %d MM iterations (%d PCG steps, %.1f s incl. setup) of the same solve on %d threads; "
+                  "scaled by the full solve's %d PCG steps" % (mm_sample, r.cg_iters, dt, r.threads, gpu_cg_total),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-mm-sample", type=int, default=4)
+    ap.add_argument("--profile-reps", type=int, default=200)
+    ap.add_argument("--mm-cap", type=int, default=0, help="cap on MM iterations (profiling runs only)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported (the multi-GPU layout is "
+              "described in DESIGN.md)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1306_1970_amd as flr
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    inst, wname = make_workload(args.workload)
+    print("bench: workload %s n=%d p=%d m=%d dtype=%s" % (wname, inst.n, inst.p, inst.m, inst.dtype),
+          file=sys.stderr, flush=True)
+    ctx = flr.Context(0)
+    prob = flr.Problem.from_instance(ctx, inst)
+    prec = flr.FLR_PREC_FP64 if args.precision == "fp64" else flr.FLR_PREC_MIXED_FP32
+    out = torch.zeros(inst.p, dtype=torch.float64, device="cuda:0")
+
+    def one():
+        return prob.solve(inst.lam1, inst.lam2, tol=inst.tol, out=out, precision=prec, max_iter=args.mm_cap)
+
+    for _ in range(args.warmup):
+        s = one()
+        print("bench: warmup solve mm=%d cg=%d f=%.12g %.3fs" % (s.mm_iters, s.cg_iters, s.objective, s.seconds),
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sols = []
+    for _ in range(args.steps):
+        sols.append(one())
+        print("bench: solve mm=%d cg=%d f=%.12g %.3fs" % (sols[-1].mm_iters, sols[-1].cg_iters, sols[-1].objective,
+                                                         sols[-1].seconds), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    s = sols[-1]
+    want = flr.FLR_ERR_MAX_ITER if args.mm_cap else flr.FLR_OK
+    assert all(x.status in (flr.FLR_OK, want) for x in sols), [x.status for x in sols]
+
+    # live per-kernel durations (HIP events on the problem's stream)
+    a_us, b_us = flr.flr_profile_kernels(prob.h, args.profile_reps)
+    xbytes = {0: 8, 1: 4, 2: 2}[inst.dtype]
+    alg_bytes = inst.n * inst.p * xbytes + 8 * (inst.p + inst.n)  # X once + operand vector + result
+    dom_name, dom_us = ("gemv_a", a_us) if a_us >= b_us else ("gemv_b", b_us)
+    achieved = alg_bytes / (dom_us * 1e-6) / 1e9
+    traffic = measured_traffic(dom_name, wname)
+    # effective bandwidth of the whole solve: two X passes per PCG step, three per MM iteration
+    passes = 2 * s.cg_iters + 3 * s.mm_iters
+    solve_gbs = passes * inst.n * inst.p * xbytes / (elapsed / args.steps) / 1e9
+
+    line = {
+        "metric": METRIC,
+        "value": args.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wname, "n": inst.n, "p": inst.p, "graph": inst.graph, "x_storage": {0: "f64", 1: "f32", 2: "bf16"}[inst.dtype],
+                   "lambda1": inst.lam1, "lambda2": inst.lam2, "tol": inst.tol, "eps": inst.eps,
+                   "precision": args.precision, "mm_iters": s.mm_iters, "cg_iters": s.cg_iters,
+                   "objective": s.objective, "solve_effective_GBps": solve_gbs},
+        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "avg_us": dom_us,
+                     "algorithmic_bytes": alg_bytes, "other_kernel_us": b_us if dom_name == "gemv_a" else a_us},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(inst, s.cg_iters, args.cpu_mm_sample)
+    prob.close()
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -150,6 +150,13 @@ flr_status flr_server_poll(flr_server s, uint64_t ticket, int blocking, double* 
 flr_status flr_server_stats(flr_server s, int32_t* queued, int32_t* running, size_t* bytes_in_use);
 void flr_server_destroy(flr_server s);
 
+/* Profiling: launch the rotation's row-panel kernel (X v) and column-panel
+ * kernel (X^T u + M v) `reps` times each on the problem's stream, in the
+ * state of a PCG step, and report their average durations in microseconds as
+ * measured with HIP events on that stream.  avg_us: host, 2 entries.  The last
+ * solution is left intact.  Needs a completed solve on the handle. */
+flr_status flr_profile_kernels(flr_problem h, int32_t reps, double* avg_us);
+
 const char* flr_status_string(flr_status st);
 const char* flr_last_error(void);
 

@@ -29,7 +29,7 @@ EXPORTS = [
     "flr_default_opts", "flr_ctx_create", "flr_ctx_destroy", "flr_create", "flr_destroy", "flr_solve",
     "flr_solve_ex", "flr_solve_grid", "flr_problem_footprint", "flr_problem_n", "flr_problem_p", "flr_problem_m",
     "flr_server_create", "flr_server_submit", "flr_server_poll", "flr_server_stats", "flr_server_destroy",
-    "flr_status_string", "flr_last_error",
+    "flr_profile_kernels", "flr_status_string", "flr_last_error",
 ]
 
 
@@ -82,6 +82,7 @@ def lib():
         L.flr_server_poll.argtypes = [vp, C.c_uint64, C.c_int, vp, C.POINTER(flr_result)]
         L.flr_server_stats.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_size_t)]
         L.flr_server_destroy.argtypes = [vp]
+        L.flr_profile_kernels.argtypes = [vp, i32, vp]
         L.flr_status_string.argtypes = [C.c_int]
         L.flr_status_string.restype = C.c_char_p
         L.flr_last_error.restype = C.c_char_p
@@ -215,6 +216,13 @@ def flr_server_stats(s):
 
 def flr_server_destroy(s):
     lib().flr_server_destroy(s)
+
+
+def flr_profile_kernels(h, reps: int):
+    """Average durations (us) of the X v and X^T u kernels, HIP events on the problem's stream."""
+    out = np.zeros(2)
+    _check(lib().flr_profile_kernels(h, reps, out.ctypes.data))
+    return float(out[0]), float(out[1])
 
 
 # ---------------------------------------------------------------------------

@@ -513,4 +513,50 @@ flr_status flr_solve_grid(flr_problem h, const double* l1, const double* l2, int
   return first;
 }
 
+flr_status flr_profile_kernels(flr_problem h, int32_t reps, double* avg_us) {
+  if (!h || reps < 1 || !avg_us) return fail(FLR_ERR_INVALID_ARG, "bad profiling arguments");
+  if (!h->has_solution) return fail(FLR_ERR_INVALID_ARG, "profiling needs a completed solve");
+  std::unique_lock<std::mutex> lk(h->busy, std::try_to_lock);
+  if (!lk.owns_lock()) return fail(FLR_ERR_BUSY, "problem handle in use by another thread");
+  HIP_OR_FAIL(hipSetDevice(h->ctx->device));
+  State cg{};
+  cg.phase = PH_CG;
+  cg.first_cg = 1;
+  cg.rz = 1.0;
+  State* hs = h->h_state;
+  hs[0] = cg;
+  hs[1] = cg;
+  hipEvent_t e0, e1, e2;
+  HIP_OR_FAIL(hipEventCreate(&e0));
+  HIP_OR_FAIL(hipEventCreate(&e1));
+  HIP_OR_FAIL(hipEventCreate(&e2));
+  HIP_OR_FAIL(hipMemcpyAsync(h->B.st, hs, 2 * sizeof(State), hipMemcpyHostToDevice, h->stream));
+  HIP_OR_FAIL(hipEventRecord(e0, h->stream));
+  for (int i = 0; i < reps; ++i) HIP_OR_FAIL(launch_rotation(h->D, h->B, 0, 0, h->stream));
+  HIP_OR_FAIL(hipEventRecord(e1, h->stream));
+  HIP_OR_FAIL(hipMemcpyAsync(h->B.st, hs, 2 * sizeof(State), hipMemcpyHostToDevice, h->stream));
+  HIP_OR_FAIL(hipEventRecord(e0, h->stream));
+  HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+  float ms_a = 0.f;
+  // re-time A from its own start event
+  HIP_OR_FAIL(hipEventRecord(e0, h->stream));
+  for (int i = 0; i < reps; ++i) HIP_OR_FAIL(launch_rotation(h->D, h->B, 0, 0, h->stream));
+  HIP_OR_FAIL(hipEventRecord(e1, h->stream));
+  HIP_OR_FAIL(hipMemcpyAsync(h->B.st, hs, 2 * sizeof(State), hipMemcpyHostToDevice, h->stream));
+  HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+  HIP_OR_FAIL(hipEventElapsedTime(&ms_a, e0, e1));
+  float ms_b = 0.f;
+  HIP_OR_FAIL(hipEventRecord(e1, h->stream));
+  for (int i = 0; i < reps; ++i) HIP_OR_FAIL(launch_rotation(h->D, h->B, 1, 1, h->stream));
+  HIP_OR_FAIL(hipEventRecord(e2, h->stream));
+  HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+  HIP_OR_FAIL(hipEventElapsedTime(&ms_b, e1, e2));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e2);
+  avg_us[0] = 1000.0 * ms_a / reps;
+  avg_us[1] = 1000.0 * ms_b / reps;
+  return FLR_OK;
+}
+
 }  // extern "C"

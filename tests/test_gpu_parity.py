@@ -89,14 +89,15 @@ def test_config2_shape_reduced(flr, ctx):
 def test_lattice(flr, ctx):
     # GPU preconditioner for the lattice keeps the index-adjacent (vertical) couplings only;
     # the oracle uses the paper's banded M.  Exact inner solves make the MM iterates agree.
+    # That preconditioner is much weaker on a 2-D graph, so the inner cap is raised for exact inner solves.
     inst = flrgen.small_instance(80, 144, "lattice", dtype=flrgen.F32, seed=6, lam1=0.2, lam2=0.5)
-    sol, ref = _pair(flr, ctx, inst, tol=1e-7)
+    sol, ref = _pair(flr, ctx, inst, tol=1e-7, max_cg=100 * inst.p)
     _check(flr, sol, ref)
 
 
 def test_all_pairs(flr, ctx):
     inst = flrgen.small_instance(30, 40, "allpairs", dtype=flrgen.F64, seed=7, lam1=0.3, lam2=0.05)
-    sol, ref = _pair(flr, ctx, inst, tol=1e-7, method=oracle.ALG1)
+    sol, ref = _pair(flr, ctx, inst, tol=1e-7, method=oracle.ALG1, max_cg=100 * inst.p)
     _check(flr, sol, ref)
 
 
