@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -96,13 +97,16 @@ Dims choose_dims(int64_t n, int64_t p, int dtype) {
   D.p_pad = round_up(p, D.c1);
   D.ldx = D.p_pad;
   D.cb1 = (int32_t)(D.p_pad / D.c1);
-  const int target = 512;
+  const char* ta = getenv("FLR_TARGET_WG_A");
+  const char* tb = getenv("FLR_TARGET_WG_B");
+  const int target = ta ? atoi(ta) : 1024;
+  const int target_b = tb ? atoi(tb) : 1024;
   int64_t rb1 = std::max<int64_t>(1, (target + D.cb1 - 1) / D.cb1);
   rb1 = std::min<int64_t>(rb1, std::max<int64_t>(1, n / 4));
   D.r1 = (int32_t)((n + rb1 - 1) / rb1);
   D.rb1 = (int32_t)((n + D.r1 - 1) / D.r1);
   D.cb2 = (int32_t)(D.p_pad / D.c2);
-  int64_t rb2 = std::max<int64_t>(1, (target + D.cb2 - 1) / D.cb2);
+  int64_t rb2 = std::max<int64_t>(1, (target_b + D.cb2 - 1) / D.cb2);
   rb2 = std::min<int64_t>(rb2, std::max<int64_t>(1, n / 4));
   int64_t r2 = (n + rb2 - 1) / rb2;
   if (r2 > kMaxR2) r2 = kMaxR2;
@@ -422,6 +426,8 @@ flr_status flr_create(flr_ctx ctx, const void* X, flr_dtype x_dtype, int64_t n, 
   CK(dalloc(h, &B.penpart, (size_t)D.nblk));
   CK(dalloc(h, &B.blk, (size_t)BK_N * (size_t)D.nblk));
   CK(dalloc(h, &B.mob, 4 * (size_t)D.nblk));
+  CK(dalloc(h, &B.carry, 2 * (size_t)D.nblk));
+  CK(dalloc(h, &B.counter, 64));
   CK(dalloc(h, &B.st, 2));
   CK(dalloc(h, &h->d_prm, 1));
   CK(dalloc(h, &flag, 1));

@@ -9,6 +9,9 @@
 //                       or, at an MM boundary: objective test, factorization, new residual
 // Each kernel reads the state written by the previous one and writes the next
 // (double-buffered by launch parity), so the host only launches and polls.
+// The last C workgroup to finish combines the per-block results (carries of
+// the partitioned tridiagonal solve, r^T z, ||r||, the inner stopping test and
+// gamma) once, so A only reads them.
 #pragma once
 #include <stdint.h>
 
@@ -46,7 +49,7 @@ struct State {
   int32_t phase, status, first, first_cg;
   int32_t mm_iter, cg_iter;
   int64_t cg_total;
-  double rz, f_old, f_new, rel_change, rel_res, nu;
+  double rz, f_old, f_new, rel_change, rel_res, nu, gamma, pad;
 };
 
 struct Dims {
@@ -85,6 +88,8 @@ struct Bufs {
   double* penpart;  // nblk
   double* blk;      // BK_N * nblk
   double* mob;      // 4 * nblk
+  double* carry;    // 2 * nblk: forward carries G, then backward carries Z
+  unsigned* counter;// blocks of the current C launch that have finished
   State* st;        // 2
   const Params* prm;
 };

@@ -67,6 +67,21 @@ __device__ inline double wg_sum(double v, double* lds) {
   return (lds[0] + lds[1]) + (lds[2] + lds[3]);
 }
 
+// Four sums over the workgroup at once (one pair of barriers).  lds: 16 doubles.
+__device__ inline void wg_sum4(double* v, double* lds) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = wave_sum(v[k]);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (l == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) lds[4 * w + k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = (lds[k] + lds[4 + k]) + (lds[8 + k] + lds[12 + k]);
+}
+
 // Affine map t -> a t + b.  compose(E, L) applies E first, then L.
 struct Aff {
   double a, b;
@@ -104,6 +119,26 @@ __device__ inline Aff wg_scan_rev(Aff m, double* lds) {
   Aff pre = {1.0, 0.0};
   for (int v = 3; v > w; --v) pre = compose(pre, {lds[2 * v], lds[2 * v + 1]});
   return compose(pre, m);
+}
+
+// Inclusive scans over the 64 lanes of one wave (no barriers).
+__device__ inline Aff wave_scan_fwd(Aff m) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    double pa = __shfl_up(m.a, d, 64), pb = __shfl_up(m.b, d, 64);
+    if (l >= d) m = compose({pa, pb}, m);
+  }
+  return m;
+}
+__device__ inline Aff wave_scan_rev(Aff m) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    double pa = __shfl_down(m.a, d, 64), pb = __shfl_down(m.b, d, 64);
+    if (l + d < 64) m = compose({pa, pb}, m);
+  }
+  return m;
 }
 
 // 2x2 projective (Moebius) product used for the continued fraction
@@ -212,126 +247,104 @@ __global__ __launch_bounds__(kWG) void k_init(Dims D, Bufs B, const double* __re
 }
 
 // ---------------------------------------------------------------------------
-// A: row-panel GEMV.  In a PCG step it first rebuilds the preconditioned
-// residual z = M^-1 r from the block-partitioned solve (carries over blocks),
-// forms r^T z and ||r||, applies the inner stopping test of Algorithm 2 and
-// the direction update p = z + gamma p; then u_part[cb] = X[:, cb] p[cb].
-// When PCG has converged (or at the MM boundary) it multiplies the iterate x.
+// A: row-panel GEMV u_part[cb] = X[rb, cb] v[cb].  In a PCG step v is the new
+// direction p = z + gamma p_old, where z = M^-1 r is rebuilt from the local
+// block solutions and the carries that the last C workgroup combined
+// (z_j = y_j + sigma_j G_k + psi_j Z_k).  Once PCG has converged, or at the
+// MM boundary, v is the iterate x.  The state is read through a restrict
+// pointer (scalar loads), so it does not wait behind the X loads.
 // ---------------------------------------------------------------------------
 template <typename XT>
-__global__ __launch_bounds__(kWG) void k_gemv_a(Dims D, Bufs B, int par) {
+__global__ __launch_bounds__(kWG) void k_gemv_a(Dims D, Bufs B, const State* __restrict__ sin,
+                                                State* __restrict__ sout) {
   constexpr int V = XV<XT>::V;
-  constexpr int NV = 4;  // 16-byte loads per lane per row
-  const State* sin = B.st + par;
-  State* sout = B.st + (par ^ 1);
+  constexpr int NV = 4;  // 16-byte loads per lane per row (the panel is 256 V columns)
+  using RAW = typename XV<XT>::raw;
   const State s = *sin;
-  if (s.phase == PH_DONE) { copy_state(sin, sout, s); return; }
-  const Params prm = *B.prm;
-
-  __shared__ double sh_v[kMaxC1];
-  __shared__ double sh_G[kMaxBlocks];
-  __shared__ double sh_Z[kMaxBlocks];
-  __shared__ double sh_m[4];
-
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wg = blockIdx.x, cb = wg % D.cb1, rb = wg / D.cb1;
-  const int tid = threadIdx.x;
-  bool use_x = true;
-  double gamma = 0.0;
+  if (wg == 0 && tid == 0) *sout = s;
+  if (s.phase == PH_DONE) return;
+  const int64_t c0 = (int64_t)cb * D.c1;
+  const int64_t r0 = (int64_t)rb * D.r1, r1 = min<int64_t>(D.n, r0 + D.r1);
+  const XT* Xb = reinterpret_cast<const XT*>(B.X);
+
+  // operand-slice inputs first (small, needed first), then the wave's first
+  // two X rows, so that waiting for the former does not wait for the latter
+  __shared__ double sh_v[kMaxC1];
+  const bool cg = s.phase == PH_CG;
   const double* pold = B.pbuf + (int64_t)(s.cg_iter & 1) * D.p_pad;
   double* pnew = B.pbuf + (int64_t)((s.cg_iter + 1) & 1) * D.p_pad;
-
-  if (s.phase == PH_CG) {
-    if (tid == 0) {
-      // carries of the partitioned tridiagonal solve: forward G_k (value of the
-      // forward sweep entering block k), backward Z_k (solution entering from the right)
-      const int K = D.nblk;
-      const double* bk = B.blk;
-      double G = 0.0;
-      sh_G[0] = 0.0;
-      for (int k = 1; k < K; ++k) {
-        G = fma(bk[BK_A * K + k - 1], G, bk[BK_B * K + k - 1]);
-        sh_G[k] = G;
-      }
-      double Z = 0.0;
-      sh_Z[K - 1] = 0.0;
-      for (int k = K - 2; k >= 0; --k) {
-        Z = bk[BK_YS * K + k + 1] + bk[BK_SIGS * K + k + 1] * sh_G[k + 1] + bk[BK_PSIS * K + k + 1] * Z;
-        sh_Z[k] = Z;
-      }
-      double rz = 0.0, rr = 0.0;
-      for (int k = 0; k < K; ++k) {
-        rz += bk[BK_RY * K + k] + sh_G[k] * bk[BK_RS * K + k] + sh_Z[k] * bk[BK_RP * K + k];
-        rr += bk[BK_RR * K + k];
-      }
-      sh_m[0] = rz;
-      sh_m[1] = rr;
+  const int K = D.nblk;
+  double fy[V], fs[V], fp[V], fo[V], fg[V], fz[V];
+#pragma unroll
+  for (int u = 0; u < V; ++u) {
+    const int64_t j = c0 + tid + u * kWG;
+    const int k = (int)(j / kBlk);
+    if (cg) {
+      fy[u] = B.yv[j];
+      fs[u] = B.sig[j];
+      fp[u] = B.psi[j];
+      fo[u] = pold[j];
+      fg[u] = B.carry[k];
+      fz[u] = B.carry[K + k];
+    } else {
+      fy[u] = B.x[j];
     }
-    __syncthreads();
-    const double rz = sh_m[0];
-    const double rn = sqrt(sh_m[1]) / prm.cnorm;
-    const bool done = !(rn > prm.inner_tol) || s.cg_iter >= prm.max_cg;
-    use_x = done;
-    if (!done) gamma = s.first_cg ? 0.0 : rz / s.rz;
-    if (wg == 0 && tid == 0) {
-      State o = s;
-      o.rel_res = rn;
-      if (done) {
-        o.phase = PH_END;
-      } else {
-        o.rz = rz;
-        o.first_cg = 0;
-      }
-      *sout = o;
+  }
+  RAW cur0[NV], cur1[NV];
+  {
+    const int64_t i0 = r0 + wave, i1 = i0 + 4;
+#pragma unroll
+    for (int t = 0; t < NV; ++t) {
+      const int64_t col = c0 + (int64_t)(t * 64 + lane) * V;
+      if (i0 < r1) cur0[t] = load16(Xb + i0 * D.ldx + col);
+      if (i1 < r1) cur1[t] = load16(Xb + i1 * D.ldx + col);
+    }
+  }
+  if (cg) {
+    const double gamma = s.gamma;
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const int64_t j = c0 + tid + u * kWG;
+      const double z = fma(fs[u], fg[u], fma(fp[u], fz[u], fy[u]));
+      const double v = fma(gamma, fo[u], z);
+      if (rb == 0) pnew[j] = v;
+      sh_v[tid + u * kWG] = v;
     }
   } else {
-    copy_state(sin, sout, s);
-  }
-
-  // operand slice of this column panel
-  const int64_t c0 = (int64_t)cb * D.c1;
-  for (int t = tid; t < D.c1; t += kWG) {
-    const int64_t j = c0 + t;
-    double v;
-    if (use_x) {
-      v = B.x[j];
-    } else {
-      const int k = (int)(j / kBlk);
-      const double z = B.yv[j] + B.sig[j] * sh_G[k] + B.psi[j] * sh_Z[k];
-      v = fma(gamma, pold[j], z);
-      if (rb == 0) pnew[j] = v;
-    }
-    sh_v[t] = v;
+#pragma unroll
+    for (int u = 0; u < V; ++u) sh_v[tid + u * kWG] = fy[u];
   }
   __syncthreads();
 
-  // u_part[cb][i] = sum_j X_ij v_j over the panel, rows r0..r1
-  const int lane = tid & 63, wave = tid >> 6;
-  const int64_t r0 = (int64_t)rb * D.r1, r1 = min<int64_t>(D.n, r0 + D.r1);
-  const int nv = D.c1 / (64 * V);  // loads per lane per row (<= NV)
   double pl[NV][V];
 #pragma unroll
   for (int t = 0; t < NV; ++t)
 #pragma unroll
-    for (int v = 0; v < V; ++v) pl[t][v] = (t < nv) ? sh_v[(t * 64 + lane) * V + v] : 0.0;
-  const XT* Xb = reinterpret_cast<const XT*>(B.X);
-  for (int64_t i = r0 + wave; i < r1; i += 4 * 2) {
-    double acc0 = 0.0, acc1 = 0.0;
-    const int64_t i1 = i + 4;
+    for (int v = 0; v < V; ++v) pl[t][v] = sh_v[(t * 64 + lane) * V + v];
+  for (int64_t i = r0 + wave; i < r1; i += 8) {
+    const int64_t i1 = i + 4, in0 = i + 8, in1 = i + 12;
     const bool has1 = i1 < r1;
+    RAW nx0[NV], nx1[NV];
 #pragma unroll
     for (int t = 0; t < NV; ++t) {
-      if (t < nv) {
-        const int64_t col = c0 + (int64_t)(t * 64 + lane) * V;
-        double xv[V];
-        XV<XT>::cvt(load16(Xb + i * D.ldx + col), xv);
+      const int64_t col = c0 + (int64_t)(t * 64 + lane) * V;
+      if (in0 < r1) nx0[t] = load16(Xb + in0 * D.ldx + col);
+      if (in1 < r1) nx1[t] = load16(Xb + in1 * D.ldx + col);
+    }
+    double acc0 = 0.0, acc1 = 0.0;
 #pragma unroll
-        for (int v = 0; v < V; ++v) acc0 = fma(xv[v], pl[t][v], acc0);
-        if (has1) {
-          double xw[V];
-          XV<XT>::cvt(load16(Xb + i1 * D.ldx + col), xw);
+    for (int t = 0; t < NV; ++t) {
+      double xv[V];
+      XV<XT>::cvt(cur0[t], xv);
 #pragma unroll
-          for (int v = 0; v < V; ++v) acc1 = fma(xw[v], pl[t][v], acc1);
-        }
+      for (int v = 0; v < V; ++v) acc0 = fma(xv[v], pl[t][v], acc0);
+      if (has1) {
+        double xw[V];
+        XV<XT>::cvt(cur1[t], xw);
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc1 = fma(xw[v], pl[t][v], acc1);
       }
     }
     acc0 = wave_sum(acc0);
@@ -339,6 +352,11 @@ __global__ __launch_bounds__(kWG) void k_gemv_a(Dims D, Bufs B, int par) {
     if (lane == 0) {
       B.upart[(int64_t)cb * D.n + i] = acc0;
       if (has1) B.upart[(int64_t)cb * D.n + i1] = acc1;
+    }
+#pragma unroll
+    for (int t = 0; t < NV; ++t) {
+      cur0[t] = nx0[t];
+      cur1[t] = nx1[t];
     }
   }
 }
@@ -360,33 +378,55 @@ __device__ inline double apply_m(const Bufs& B, const Params& prm, int64_t j, co
 // the penalty sums of f, and each block's factorization product.
 // ---------------------------------------------------------------------------
 template <typename XT>
-__global__ __launch_bounds__(kWG) void k_gemv_b(Dims D, Bufs B, int par) {
+__global__ __launch_bounds__(kWG) void k_gemv_b(Dims D, Bufs B, const State* __restrict__ sin,
+                                                State* __restrict__ sout, const Params* __restrict__ prmp) {
   constexpr int V = XV<XT>::V;
-  const State* sin = B.st + par;
-  State* sout = B.st + (par ^ 1);
+  constexpr int RU = 8;  // rows per wave in flight
+  using RAW = typename XV<XT>::raw;
   const State s = *sin;
-  copy_state(sin, sout, s);
+  const int wg = blockIdx.x, tid = threadIdx.x;
+  if (wg == 0 && tid == 0) *sout = s;
   if (s.phase == PH_DONE) return;
-  const Params prm = *B.prm;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int ngemm = D.cb2 * D.rb2;
+  const int cb = wg % D.cb2, rb = wg / D.cb2;
+  const int64_t r0 = (int64_t)rb * D.r2, r1 = wg < ngemm ? min<int64_t>(D.n, r0 + D.r2) : r0;
+  const int64_t c0 = (int64_t)cb * D.c2 + lane * V;
+  const XT* Xb = reinterpret_cast<const XT*>(B.X);
+  const Params prm = *prmp;
   const bool cg = s.phase == PH_CG;
   const double* pv = cg ? (B.pbuf + (int64_t)((s.cg_iter + 1) & 1) * D.p_pad) : B.x;
 
   __shared__ double sh_u[kMaxR2];
   __shared__ double sh_red[4][64 * 8];
-  __shared__ double sh_s[4];
+  __shared__ double sh_s[16];
   __shared__ double sh_d[kBlk], sh_e[kBlk];
 
-  const int wg = blockIdx.x, tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int ngemm = D.cb2 * D.rb2;
+  // u for the first 256 panel rows (sum of the A partials), issued before
+  // the X rows so that waiting for it does not wait for them
+  constexpr int CBMAX = 12;
+  const int nr = (int)(r1 - r0);
+  double upre[CBMAX];
+#pragma unroll
+  for (int q = 0; q < CBMAX; ++q) upre[q] = (tid < nr && q < D.cb1) ? B.upart[(int64_t)q * D.n + r0 + tid] : 0.0;
+  RAW cur[RU];
+#pragma unroll
+  for (int u = 0; u < RU; ++u) {
+    const int64_t i = r0 + wave + 4 * u;
+    if (i < r1) cur[u] = load16(Xb + i * D.ldx + c0);
+  }
+
   if (wg < ngemm) {
-    const int cb = wg % D.cb2, rb = wg / D.cb2;
-    const int64_t r0 = (int64_t)rb * D.r2, r1 = min<int64_t>(D.n, r0 + D.r2);
-    const int nr = (int)(r1 - r0);
     double loss = 0.0;
     for (int t = tid; t < nr; t += kWG) {
       double u = 0.0;
-      for (int q = 0; q < D.cb1; ++q) u += B.upart[(int64_t)q * D.n + r0 + t];
+      if (t == tid) {
+#pragma unroll
+        for (int q = 0; q < CBMAX; ++q) u += upre[q];
+        for (int q = CBMAX; q < D.cb1; ++q) u += B.upart[(int64_t)q * D.n + r0 + t];
+      } else {
+        for (int q = 0; q < D.cb1; ++q) u += B.upart[(int64_t)q * D.n + r0 + t];
+      }
       sh_u[t] = u;
       if (!cg && cb == 0) {
         const double dlt = B.y[r0 + t] - u;
@@ -394,33 +434,29 @@ __global__ __launch_bounds__(kWG) void k_gemv_b(Dims D, Bufs B, int par) {
       }
     }
     __syncthreads();
-    const int64_t c0 = (int64_t)cb * D.c2 + lane * V;
     double acc[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[v] = 0.0;
-    const XT* Xb = reinterpret_cast<const XT*>(B.X);
-    int64_t i = r0 + wave;
-    for (; i + 12 < r1; i += 16) {
-      double x0[V], x1[V], x2[V], x3[V];
-      XV<XT>::cvt(load16(Xb + i * D.ldx + c0), x0);
-      XV<XT>::cvt(load16(Xb + (i + 4) * D.ldx + c0), x1);
-      XV<XT>::cvt(load16(Xb + (i + 8) * D.ldx + c0), x2);
-      XV<XT>::cvt(load16(Xb + (i + 12) * D.ldx + c0), x3);
-      const double u0 = sh_u[i - r0], u1 = sh_u[i + 4 - r0], u2 = sh_u[i + 8 - r0], u3 = sh_u[i + 12 - r0];
+    for (int64_t i = r0 + wave; i < r1; i += 4 * RU) {
+      RAW nxt[RU];
 #pragma unroll
-      for (int v = 0; v < V; ++v) {
-        acc[v] = fma(x0[v], u0, acc[v]);
-        acc[v] = fma(x1[v], u1, acc[v]);
-        acc[v] = fma(x2[v], u2, acc[v]);
-        acc[v] = fma(x3[v], u3, acc[v]);
+      for (int u = 0; u < RU; ++u) {
+        const int64_t ii = i + 4 * RU + 4 * u;
+        if (ii < r1) nxt[u] = load16(Xb + ii * D.ldx + c0);
       }
-    }
-    for (; i < r1; i += 4) {
-      double x0[V];
-      XV<XT>::cvt(load16(Xb + i * D.ldx + c0), x0);
-      const double u0 = sh_u[i - r0];
 #pragma unroll
-      for (int v = 0; v < V; ++v) acc[v] = fma(x0[v], u0, acc[v]);
+      for (int u = 0; u < RU; ++u) {
+        const int64_t ii = i + 4 * u;
+        if (ii < r1) {
+          double xv[V];
+          XV<XT>::cvt(cur[u], xv);
+          const double uu = sh_u[ii - r0];
+#pragma unroll
+          for (int v = 0; v < V; ++v) acc[v] = fma(xv[v], uu, acc[v]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < RU; ++u) cur[u] = nxt[u];
     }
 #pragma unroll
     for (int v = 0; v < V; ++v) sh_red[wave][lane * V + v] = acc[v];
@@ -461,15 +497,11 @@ __global__ __launch_bounds__(kWG) void k_gemv_b(Dims D, Bufs B, int par) {
         B.w[q] = wq;
         wsum += wq;
         if (k > j) pen2 += dlt;
+        if (k == j - 1 && !prm.jacobi) ej = -prm.lam2 * wq;
       }
       pen = prm.lam1 * fabs(xj) + prm.lam2 * pen2;
       dj = prm.lam1 * aj + prm.lam2 * wsum;
-      if (prm.jacobi) {
-        dj += B.s[j];
-      } else if (B.prevpos[j] >= 0) {
-        // edge (j-1, j): its weight was computed for row j above (same |b_j - b_k| both ways)
-        ej = -prm.lam2 * (1.0 / (fabs(xj - B.x[j - 1]) + prm.eps));
-      }
+      if (prm.jacobi) dj += B.s[j];
       B.d[j] = dj;
       B.e[j] = ej;
     } else if (j < D.p_pad) {
@@ -497,8 +529,8 @@ __global__ __launch_bounds__(kWG) void k_gemv_b(Dims D, Bufs B, int par) {
 
 // Zero-inflow local solve of the block for the current residual r_j and the
 // block scalars that the next A launch combines into the global solution:
-//   forward  g_j = r_j - L_j g_{j-1}         (L D L^T, forward sweep)
-//   backward y_j = g_j / D_j - L_{j+1} y_{j+1} (backward sweep)
+//   forward  g_j = r_j - L_j g_{j-1}           (L D L^T, forward sweep)
+//   backward y_j = g_j / D_j - L_{j+1} y_{j+1}   (backward sweep)
 __device__ inline void block_local_solve(const Dims& D, const Bufs& B, int b, int64_t j, double rj, double Lj,
                                          double Lnext, double invDj, double sigj, double psij, double* lds,
                                          double* lds2) {
@@ -512,18 +544,204 @@ __device__ inline void block_local_solve(const Dims& D, const Bufs& B, int b, in
   __syncthreads();
   if (tid == kBlk - 1) lds2[0] = g;
   if (tid == 0) lds2[1] = yj;
-  const double ry = wg_sum(rj * yj, lds);
-  const double rs = wg_sum(rj * sigj, lds);
-  const double rp = wg_sum(rj * psij, lds);
-  const double rr = wg_sum(rj * rj, lds);
+  double sums[4] = {rj * yj, rj * sigj, rj * psij, rj * rj};
+  wg_sum4(sums, lds);
   if (tid == 0) {
     B.blk[BK_B * K + b] = lds2[0];
     B.blk[BK_YS * K + b] = lds2[1];
-    B.blk[BK_RY * K + b] = ry;
-    B.blk[BK_RS * K + b] = rs;
-    B.blk[BK_RP * K + b] = rp;
-    B.blk[BK_RR * K + b] = rr;
+    B.blk[BK_RY * K + b] = sums[0];
+    B.blk[BK_RS * K + b] = sums[1];
+    B.blk[BK_RP * K + b] = sums[2];
+    B.blk[BK_RR * K + b] = sums[3];
   }
+}
+
+// Wave-level variant of combine_blocks for K <= 256 (4 blocks per lane),
+// run by wave 0 alone: shuffles only, no barriers.
+__device__ void combine_blocks_wave(const Dims& D, const Bufs& B, const Params& prm, State o, double rz_prev,
+                                    bool first_step, State* __restrict__ sout) {
+  constexpr int E = 4;
+  const int l = threadIdx.x & 63;
+  const int K = D.nblk;
+  const int e = (K + 63) / 64;
+  const double* bk = B.blk;
+  const int k0 = l * e;
+  double fA[E], fB[E], fRY[E], fRS[E], fRP[E], fRR[E], nPS[E], nYS[E], nSS[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int k = k0 + i;
+    const bool ok = i < e && k < K;
+    const bool okn = i < e && k + 1 < K;
+    fA[i] = ok ? bk[BK_A * K + k] : 1.0;
+    fB[i] = ok ? bk[BK_B * K + k] : 0.0;
+    fRY[i] = ok ? bk[BK_RY * K + k] : 0.0;
+    fRS[i] = ok ? bk[BK_RS * K + k] : 0.0;
+    fRP[i] = ok ? bk[BK_RP * K + k] : 0.0;
+    fRR[i] = ok ? bk[BK_RR * K + k] : 0.0;
+    nPS[i] = okn ? bk[BK_PSIS * K + k + 1] : 0.0;
+    nYS[i] = okn ? bk[BK_YS * K + k + 1] : 0.0;
+    nSS[i] = okn ? bk[BK_SIGS * K + k + 1] : 0.0;
+  }
+  Aff m = {1.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < E; ++i)
+    if (i < e && k0 + i < K) m = compose(m, {fA[i], fB[i]});
+  const Aff fin = wave_scan_fwd(m);
+  double G = __shfl_up(fin.b, 1, 64);
+  if (l == 0) G = 0.0;
+  double Gk[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    Gk[i] = G;
+    if (i < e && k0 + i < K) G = fma(fA[i], G, fB[i]);
+  }
+  Aff mb = {1.0, 0.0};
+#pragma unroll
+  for (int i = E - 1; i >= 0; --i) {
+    const int k = k0 + i;
+    const double Gn = (i + 1 < e) ? Gk[(i + 1) < E ? i + 1 : 0] : G;
+    if (i < e && k < K - 1) {
+      mb = compose(mb, {nPS[i], fma(nSS[i], Gn, nYS[i])});
+    } else if (i < e && k == K - 1) {
+      mb = compose(mb, {0.0, 0.0});
+    }
+  }
+  const Aff finb = wave_scan_rev(mb);
+  double Z = __shfl_down(finb.b, 1, 64);
+  if (l == 63) Z = 0.0;
+  double rzp = 0.0, rrp = 0.0;
+#pragma unroll
+  for (int i = E - 1; i >= 0; --i) {
+    const int k = k0 + i;
+    if (i < e && k < K) {
+      const double Gn = (i + 1 < e) ? Gk[(i + 1) < E ? i + 1 : 0] : G;
+      Z = (k < K - 1) ? fma(nPS[i], Z, fma(nSS[i], Gn, nYS[i])) : 0.0;
+      B.carry[k] = Gk[i];
+      B.carry[K + k] = Z;
+      rzp += fRY[i] + Gk[i] * fRS[i] + Z * fRP[i];
+      rrp += fRR[i];
+    }
+  }
+  const double rz = wave_sum(rzp);
+  const double rr = wave_sum(rrp);
+  if (l == 0) {
+    const double rn = sqrt(rr) / prm.cnorm;
+    const bool done = !(rn > prm.inner_tol) || o.cg_iter >= prm.max_cg;
+    o.rel_res = rn;
+    o.rz = rz;
+    o.gamma = first_step ? 0.0 : rz / rz_prev;
+    o.phase = done ? PH_END : PH_CG;
+    *sout = o;
+    *B.counter = 0u;
+  }
+}
+
+// Called by every thread of the last C workgroup to finish, once the block
+// scalars of all blocks are visible: carries of the partitioned tridiagonal
+// solve over the blocks (forward G_k = forward-sweep value entering block k,
+// backward Z_k = solution value entering block k from the right), r^T z,
+// ||r||, the inner stopping test of Algorithm 2 and gamma = r^T z / r_old^T z_old.
+__device__ void combine_blocks(const Dims& D, const Bufs& B, const Params& prm, State o, double rz_prev,
+                               bool first_step, State* __restrict__ sout, double* sh_m, double* sh_G, double* sh_Z) {
+  constexpr int EMAX = kMaxBlocks / kWG;
+  const int tid = threadIdx.x;
+  const int K = D.nblk;
+  const int e4 = (K + kWG - 1) / kWG;
+  const double* bk = B.blk;
+  const int k0 = tid * e4;
+  double fA[EMAX], fB[EMAX], fRY[EMAX], fRS[EMAX], fRP[EMAX], fRR[EMAX], nPS[EMAX], nYS[EMAX], nSS[EMAX];
+#pragma unroll
+  for (int i = 0; i < EMAX; ++i) {
+    const int k = k0 + i;
+    const bool ok = i < e4 && k < K;
+    const bool okn = i < e4 && k + 1 < K;
+    fA[i] = ok ? bk[BK_A * K + k] : 1.0;
+    fB[i] = ok ? bk[BK_B * K + k] : 0.0;
+    fRY[i] = ok ? bk[BK_RY * K + k] : 0.0;
+    fRS[i] = ok ? bk[BK_RS * K + k] : 0.0;
+    fRP[i] = ok ? bk[BK_RP * K + k] : 0.0;
+    fRR[i] = ok ? bk[BK_RR * K + k] : 0.0;
+    nPS[i] = okn ? bk[BK_PSIS * K + k + 1] : 0.0;
+    nYS[i] = okn ? bk[BK_YS * K + k + 1] : 0.0;
+    nSS[i] = okn ? bk[BK_SIGS * K + k + 1] : 0.0;
+  }
+  Aff m = {1.0, 0.0};
+#pragma unroll
+  for (int i = 0; i < EMAX; ++i)
+    if (i < e4 && k0 + i < K) m = compose(m, {fA[i], fB[i]});
+  const Aff fin = wg_scan_fwd(m, sh_m + 8);
+  __syncthreads();
+  sh_G[kMaxBlocks - 1 - tid] = fin.b;  // scratch: inclusive result per thread
+  __syncthreads();
+  double G = tid == 0 ? 0.0 : sh_G[kMaxBlocks - tid];
+  __syncthreads();
+  double Gk[EMAX];
+#pragma unroll
+  for (int i = 0; i < EMAX; ++i) {
+    Gk[i] = G;
+    if (i < e4 && k0 + i < K) G = fma(fA[i], G, fB[i]);
+  }
+  // Z_k = psis_{k+1} Z_{k+1} + ys_{k+1} + sigs_{k+1} G_{k+1},  Z_{K-1} = 0
+  Aff mb = {1.0, 0.0};
+#pragma unroll
+  for (int i = EMAX - 1; i >= 0; --i) {
+    const int k = k0 + i;
+    const double Gn = (i + 1 < e4) ? Gk[(i + 1) < EMAX ? i + 1 : 0] : G;
+    if (i < e4 && k < K - 1) {
+      mb = compose(mb, {nPS[i], fma(nSS[i], Gn, nYS[i])});
+    } else if (i < e4 && k == K - 1) {
+      mb = compose(mb, {0.0, 0.0});
+    }
+  }
+  const Aff finb = wg_scan_rev(mb, sh_m + 8);
+  __syncthreads();
+  sh_Z[kMaxBlocks - 1 - tid] = finb.b;
+  __syncthreads();
+  double Z = tid == kWG - 1 ? 0.0 : sh_Z[kMaxBlocks - 2 - tid];
+  double rzp = 0.0, rrp = 0.0;
+#pragma unroll
+  for (int i = EMAX - 1; i >= 0; --i) {
+    const int k = k0 + i;
+    if (i < e4 && k < K) {
+      const double Gn = (i + 1 < e4) ? Gk[(i + 1) < EMAX ? i + 1 : 0] : G;
+      Z = (k < K - 1) ? fma(nPS[i], Z, fma(nSS[i], Gn, nYS[i])) : 0.0;
+      B.carry[k] = Gk[i];
+      B.carry[K + k] = Z;
+      rzp += fRY[i] + Gk[i] * fRS[i] + Z * fRP[i];
+      rrp += fRR[i];
+    }
+  }
+  const double rz = wg_sum(rzp, sh_m + 8);
+  const double rr = wg_sum(rrp, sh_m + 8);
+  if (tid == 0) {
+    const double rn = sqrt(rr) / prm.cnorm;
+    const bool done = !(rn > prm.inner_tol) || o.cg_iter >= prm.max_cg;
+    o.rel_res = rn;
+    o.rz = rz;
+    o.gamma = first_step ? 0.0 : rz / rz_prev;
+    o.phase = done ? PH_END : PH_CG;
+    *sout = o;
+    *B.counter = 0u;
+  }
+}
+
+// True in the one workgroup that finishes last; its loads after this point
+// see every other workgroup's block scalars (release by each block before its
+// arrival, acquire by the last one).  No workgroup waits for another.
+// Only thread 0 wrote the block scalars, so only it needs to publish them;
+// the last block's acquire fence by thread 0 precedes the barrier after which
+// all of its threads read the other blocks' scalars.
+__device__ inline bool arrive_last(const Bufs& B, int nblocks, int* flag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned prev = atomicAdd(B.counter, 1u);
+    const bool last = prev == (unsigned)(nblocks - 1);
+    if (last) __threadfence();
+    *flag = last;
+  }
+  __syncthreads();
+  return *flag != 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -533,27 +751,49 @@ __device__ inline void block_local_solve(const Dims& D, const Bufs& B, int b, in
 // relative-change test of Algorithm 2, and - if continuing - the LDL^T
 // factorization of the tridiagonal M (carry of the block products, then the
 // block's own continued fraction), the gain vectors, r0 = c - Q x0 and its
-// local solve.
+// local solve.  The last workgroup to finish combines the blocks.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kWG) void k_block(Dims D, Bufs B, int par) {
-  const State* sin = B.st + par;
-  State* sout = B.st + (par ^ 1);
+__global__ __launch_bounds__(kWG) void k_block(Dims D, Bufs B, const State* __restrict__ sin,
+                                               State* __restrict__ sout, const Params* __restrict__ prmp) {
+  constexpr int QMAX = 16;  // row panels whose partial products are prefetched
   const State s = *sin;
-  if (s.phase == PH_DONE) { copy_state(sin, sout, s); return; }
-  const Params prm = *B.prm;
-  __shared__ double lds[16];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  if (s.phase == PH_DONE) {
+    if (b == 0 && tid == 0) *sout = s;
+    return;
+  }
+  const int64_t j = (int64_t)b * kBlk + tid;
+  const bool real = j < D.p;
+  const Params prm = *prmp;
+  __shared__ double lds[24];
   __shared__ double lds2[4];
   __shared__ double sh_D[kBlk];
   __shared__ double sh_L[kBlk + 1];
-  const int b = blockIdx.x, tid = threadIdx.x;
-  const int64_t j = (int64_t)b * kBlk + tid;
-  const bool real = j < D.p;
-  const int ngemm = D.cb2 * D.rb2;
+  __shared__ double sh_mob[4][kWG];
+  __shared__ double sh_G[kMaxBlocks], sh_Z[kMaxBlocks];
+  __shared__ int sh_flag;
 
   if (s.phase == PH_CG) {
-    // p^T Q p from the B partials (fixed order)
+    // every input of this step in one round of loads
+    const double* pv = B.pbuf + (int64_t)((s.cg_iter + 1) & 1) * D.p_pad;
     double part = 0.0;
     for (int q = tid; q < D.gridB; q += kWG) part += B.pqpart[q];
+    double qp[QMAX];
+#pragma unroll
+    for (int rb = 0; rb < QMAX; ++rb) qp[rb] = (real && rb < D.rb2) ? B.qpart[(int64_t)rb * D.p_pad + j] : 0.0;
+    double qrest = 0.0;
+    for (int rb = QMAX; rb < D.rb2; ++rb) qrest += real ? B.qpart[(int64_t)rb * D.p_pad + j] : 0.0;
+    double pj = 0.0, xj = 0.0, rj0 = 0.0, Lj = 0.0, invDj = 0.0, sigj = 0.0, psij = 0.0, Lnb = 0.0;
+    if (real) {
+      pj = pv[j];
+      xj = B.x[j];
+      rj0 = B.r[j];
+      Lj = B.L[j];
+      invDj = B.invD[j];
+      sigj = B.sig[j];
+      psij = B.psi[j];
+    }
+    if (tid == 0) Lnb = (j + kBlk < D.p) ? B.L[j + kBlk] : 0.0;
     const double pq = wg_sum(part, lds);
     const double nu = s.rz / pq;
     if (!(pq > 0.0) || !isfinite(nu)) {
@@ -565,34 +805,51 @@ __global__ __launch_bounds__(kWG) void k_block(Dims D, Bufs B, int par) {
       }
       return;
     }
-    const double* pv = B.pbuf + (int64_t)((s.cg_iter + 1) & 1) * D.p_pad;
-    double rj = 0.0, Lj = 0.0, invDj = 0.0, sigj = 0.0, psij = 0.0;
+    double rj = 0.0;
     if (real) {
       double q = 0.0;
-      for (int rb = 0; rb < D.rb2; ++rb) q += B.qpart[(int64_t)rb * D.p_pad + j];
-      B.x[j] = fma(nu, pv[j], B.x[j]);
-      rj = fma(-nu, q, B.r[j]);
+#pragma unroll
+      for (int rb = 0; rb < QMAX; ++rb) q += qp[rb];
+      q += qrest;
+      B.x[j] = fma(nu, pj, xj);
+      rj = fma(-nu, q, rj0);
       B.r[j] = rj;
-      Lj = B.L[j];
-      invDj = B.invD[j];
-      sigj = B.sig[j];
-      psij = B.psi[j];
     }
     sh_L[tid] = Lj;
-    if (tid == 0) sh_L[kBlk] = (j + kBlk < D.p) ? B.L[j + kBlk] : 0.0;
+    if (tid == 0) sh_L[kBlk] = Lnb;
     __syncthreads();
     block_local_solve(D, B, b, j, rj, Lj, sh_L[tid + 1], invDj, sigj, psij, lds, lds2);
-    if (b == 0 && tid == 0) {
+    if (arrive_last(B, D.nblk, &sh_flag)) {
       State o = s;
       o.cg_iter = s.cg_iter + 1;
       o.cg_total = s.cg_total + 1;
       o.nu = nu;
-      *sout = o;
+      if (D.nblk <= 4 * 64) {
+        if (tid < 64) combine_blocks_wave(D, B, prm, o, s.rz, false, sout);
+      } else {
+        combine_blocks(D, B, prm, o, s.rz, false, sout, lds, sh_G, sh_Z);
+      }
     }
     return;
   }
 
   // ---- MM boundary ----
+  // inputs that do not depend on the decision, loaded up front
+  double dj = 1.0, ej = 0.0, cj = 0.0, qsum = 0.0, enext = 0.0;
+  if (real) {
+    dj = B.d[j];
+    ej = B.e[j];
+    cj = B.c[j];
+    for (int rb = 0; rb < D.rb2; ++rb) qsum += B.qpart[(int64_t)rb * D.p_pad + j];
+  }
+  if (tid == kBlk - 1 && j + 1 < D.p) enext = B.e[j + 1];
+  // ordered product of the previous blocks' factorization matrices
+  const int e4 = (b + kWG - 1) / kWG;
+  Mob P = {1.0, 0.0, 0.0, 1.0};
+  for (int i = 0; i < e4; ++i) {
+    const int k = tid * e4 + i;
+    if (k < b) P = mob_mul({B.mob[4 * k], B.mob[4 * k + 1], B.mob[4 * k + 2], B.mob[4 * k + 3]}, P);
+  }
   // f(b) = loss + penalties (identical arithmetic in every workgroup)
   double fpart = 0.0;
   for (int q = tid; q < D.rb2; q += kWG) fpart += B.losspart[q];
@@ -627,58 +884,53 @@ __global__ __launch_bounds__(kWG) void k_block(Dims D, Bufs B, int par) {
     return;
   }
   o.f_old = f_new;
-  o.phase = PH_CG;
   o.first_cg = 1;
   o.cg_iter = 0;
 
-  // factorization: D entering this block from the product of the previous blocks
+  // ordered tree reduction of the per-thread products (later blocks on the left)
+  sh_mob[0][tid] = P.m00;
+  sh_mob[1][tid] = P.m01;
+  sh_mob[2][tid] = P.m10;
+  sh_mob[3][tid] = P.m11;
+  sh_D[tid] = dj;
+  sh_L[tid] = ej;
+  __syncthreads();
+  for (int w = 1; w < kWG; w <<= 1) {
+    if ((tid & (2 * w - 1)) == 0 && tid + w < kWG) {
+      const Mob lo = {sh_mob[0][tid], sh_mob[1][tid], sh_mob[2][tid], sh_mob[3][tid]};
+      const Mob hi = {sh_mob[0][tid + w], sh_mob[1][tid + w], sh_mob[2][tid + w], sh_mob[3][tid + w]};
+      const Mob pr = mob_mul(hi, lo);
+      sh_mob[0][tid] = pr.m00;
+      sh_mob[1][tid] = pr.m01;
+      sh_mob[2][tid] = pr.m10;
+      sh_mob[3][tid] = pr.m11;
+    }
+    __syncthreads();
+  }
+  // factorization D_j = d_j - e_j^2 / D_{j-1} through the block, from the carried-in D
   if (tid == 0) {
     double Din = INFINITY;
-    if (b > 0) {
-      double va = 1.0, vb = 0.0;
-      for (int k = 0; k < b; ++k) {
-        const double m00 = B.mob[4 * k], m01 = B.mob[4 * k + 1], m10 = B.mob[4 * k + 2], m11 = B.mob[4 * k + 3];
-        double na = m00 * va + m01 * vb, nb = m10 * va + m11 * vb;
-        double mx = fmax(fabs(na), fabs(nb));
-        if (mx > 0.0 && isfinite(mx)) {
-          const int ex = ilogb(mx);
-          na = ldexp(na, -ex);
-          nb = ldexp(nb, -ex);
-        }
-        va = na;
-        vb = nb;
-      }
-      Din = va / vb;
-    }
+    if (b > 0) Din = sh_mob[0][0] / sh_mob[2][0];  // product applied to (1, 0)
+    lds2[2] = Din;
     double Dp = Din;
     for (int t = 0; t < kBlk; ++t) {
-      const int64_t jj = (int64_t)b * kBlk + t;
-      if (jj >= D.p) { sh_D[t] = 1.0; continue; }
-      const double et = B.e[jj];
-      const double Dj = et != 0.0 ? B.d[jj] - et * (et / Dp) : B.d[jj];
-      sh_D[t] = Dj;
-      Dp = Dj;
+      if ((int64_t)b * kBlk + t >= D.p) break;
+      const double et = sh_L[t];
+      const double dd = et != 0.0 ? sh_D[t] - et * (et / Dp) : sh_D[t];
+      sh_D[t] = dd;
+      Dp = dd;
     }
-    lds2[2] = Din;
   }
   __syncthreads();
   double Lj = 0.0, invDj = 0.0;
   if (real) {
-    const double ej = B.e[j];
     const double Dm1 = tid == 0 ? lds2[2] : sh_D[tid - 1];
     Lj = ej != 0.0 ? ej / Dm1 : 0.0;
     invDj = 1.0 / sh_D[tid];
   }
+  __syncthreads();
   sh_L[tid] = Lj;
-  if (tid == kBlk - 1) {
-    const int64_t jn = j + 1;
-    double Ln = 0.0;
-    if (real && jn < D.p) {
-      const double en = B.e[jn];
-      Ln = en != 0.0 ? en / sh_D[tid] : 0.0;
-    }
-    sh_L[kBlk] = Ln;
-  }
+  if (tid == kBlk - 1) sh_L[kBlk] = (real && enext != 0.0) ? enext / sh_D[tid] : 0.0;
   __syncthreads();
   const double Lnext = sh_L[tid + 1];
   // phi_j = prod_{i=start..j} (-L_i); psi_j = prod_{i=j+1..end+1} (-L_i);
@@ -707,14 +959,17 @@ __global__ __launch_bounds__(kWG) void k_block(Dims D, Bufs B, int par) {
   // r0 = c - (X^T X + M) x0 with x0 the MM iterate (Algorithm 2)
   double rj = 0.0;
   if (real) {
-    double q = 0.0;
-    for (int rb = 0; rb < D.rb2; ++rb) q += B.qpart[(int64_t)rb * D.p_pad + j];
-    rj = B.c[j] - (q + apply_m(B, prm, j, B.x));
+    rj = cj - (qsum + apply_m(B, prm, j, B.x));
     B.r[j] = rj;
   }
-  (void)ngemm;
   block_local_solve(D, B, b, j, rj, Lj, Lnext, invDj, sigj, psij, lds, lds2);
-  if (b == 0 && tid == 0) *sout = o;
+  if (arrive_last(B, D.nblk, &sh_flag)) {
+    if (D.nblk <= 4 * 64) {
+      if (tid < 64) combine_blocks_wave(D, B, prm, o, 0.0, true, sout);
+    } else {
+      combine_blocks(D, B, prm, o, 0.0, true, sout, lds, sh_G, sh_Z);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -722,15 +977,17 @@ __global__ __launch_bounds__(kWG) void k_block(Dims D, Bufs B, int par) {
 // ---------------------------------------------------------------------------
 template <typename XT>
 static hipError_t launch_rotation_t(const Dims& D, const Bufs& B, int par, int which, hipStream_t st) {
+  const State* sin = B.st + par;
+  State* sout = B.st + (par ^ 1);
   switch (which) {
     case 0:
-      hipLaunchKernelGGL(k_gemv_a<XT>, dim3(D.cb1 * D.rb1), dim3(kWG), 0, st, D, B, par);
+      hipLaunchKernelGGL(k_gemv_a<XT>, dim3(D.cb1 * D.rb1), dim3(kWG), 0, st, D, B, sin, sout);
       break;
     case 1:
-      hipLaunchKernelGGL(k_gemv_b<XT>, dim3(D.gridB), dim3(kWG), 0, st, D, B, par);
+      hipLaunchKernelGGL(k_gemv_b<XT>, dim3(D.gridB), dim3(kWG), 0, st, D, B, sin, sout, B.prm);
       break;
     default:
-      hipLaunchKernelGGL(k_block, dim3(D.nblk), dim3(kWG), 0, st, D, B, par);
+      hipLaunchKernelGGL(k_block, dim3(D.nblk), dim3(kWG), 0, st, D, B, sin, sout, B.prm);
       break;
   }
   return hipGetLastError();

@@ -114,7 +114,7 @@ def test_flsa_lambda1_zero_uses_jacobi(flr, ctx):
     beta = np.repeat(rng.uniform(-2, 2, 6), 50)
     y = beta + 0.3 * rng.standard_normal(p)
     inst = flrgen.Instance("flsa_chain", np.eye(p), flrgen.F64, y, flrgen.chain_edges(p), beta, 0.0, 0.7)
-    sol, ref = _pair(flr, ctx, inst, tol=1e-7, method=oracle.ALG1)
+    sol, ref = _pair(flr, ctx, inst, tol=1e-7, method=oracle.ALG1, max_cg=100 * p)
     _check(flr, sol, ref)
 
 
