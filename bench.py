@@ -94,6 +94,9 @@ def main():
     ap.add_argument("--cpu-mm-sample", type=int, default=4)
     ap.add_argument("--profile-reps", type=int, default=200)
     ap.add_argument("--mm-cap", type=int, default=0, help="cap on MM iterations (profiling runs only)")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="after the solves, copy this many MiB with a plain device copy 3 times (reference "
+                         "dispatches for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported (the multi-GPU layout is "
@@ -169,6 +172,16 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(inst, s.cg_iters, args.cpu_mm_sample)
+    if args.calibrate_copy:
+        nb = args.calibrate_copy * (1 << 20)
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            evict = torch.full((nb // 4,), 2.0, dtype=torch.float32, device="cuda:0")  # pushes src out of the LLC
+            del evict
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["calibration_copy_bytes"] = nb
     prob.close()
     ctx.close()
     print(json.dumps(line), flush=True)

@@ -14,6 +14,7 @@
 
 #include "../../include/flr.h"
 #include "flr_internal.h"
+#include "flr_problem.h"
 
 namespace flr {
 hipError_t launch_rotation(const Dims& D, const Bufs& B, int par, int which, hipStream_t st);
@@ -39,36 +40,6 @@ static flr_status fail(flr_status st, const std::string& msg) {
       return fail(e_ == hipErrorOutOfMemory ? FLR_ERR_OUT_OF_MEMORY : FLR_ERR_DEVICE,                       \
                   std::string(#expr) + ": " + hipGetErrorString(e_));                                       \
   } while (0)
-
-struct flr_ctx_s {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
-};
-
-// Number of A/B/C rounds captured in one graph (3*S launches; S even keeps
-// the state parity fixed per node).
-static constexpr int kRounds = 16;
-
-struct flr_problem_s {
-  flr_ctx ctx = nullptr;
-  Dims D{};
-  Bufs B{};
-  int64_t m = 0;
-  int64_t nnz = 0;
-  double cnorm = 0.0;
-  hipStream_t stream = nullptr;
-  Params* d_prm = nullptr;
-  Params* h_prm = nullptr;  // pinned
-  State* h_state = nullptr; // pinned, 2 slots
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  std::vector<void*> allocs;
-  size_t footprint = 0;
-  bool has_solution = false;
-  std::mutex busy;
-};
 
 namespace {
 
@@ -245,6 +216,7 @@ flr_status solve_locked(flr_problem h, double l1, double l2, double tol, const f
   return run_solve(h, l1, l2, tol, o, beta_out, res);
 }
 std::mutex& problem_mutex(flr_problem h) { return h->busy; }
+bool is_device_pointer(const void* p) { return is_device_ptr(p); }
 size_t problem_footprint(flr_problem h) { return h->footprint; }
 int problem_device(flr_problem h) { return h->ctx->device; }
 void set_last_error(const std::string& s) { g_last_error = s; }
@@ -307,6 +279,8 @@ void flr_ctx_destroy(flr_ctx c) {
 static void problem_free(flr_problem h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
+  flr::grid_free(h);
+  if (h->X64) (void)hipFree(h->X64);
   if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
   if (h->graph) (void)hipGraphDestroy(h->graph);
   for (void* p : h->allocs) (void)hipFree(p);
@@ -496,27 +470,6 @@ flr_status flr_solve(flr_problem h, double l1, double l2, double tol, double* be
     if (iterations_out) *iterations_out = r.mm_iters;
   }
   return st;
-}
-
-flr_status flr_solve_grid(flr_problem h, const double* l1, const double* l2, int32_t B, double tol,
-                          const flr_solve_opts* opts, double* beta_out, flr_result* res) {
-  if (!h || !l1 || !l2 || B < 1) return fail(FLR_ERR_INVALID_ARG, "bad grid arguments");
-  for (int32_t i = 0; i < B; ++i) {
-    flr_status v = validate_lambdas(l1[i], l2[i], tol);
-    if (v != FLR_OK) return v;
-  }
-  flr_status first = FLR_OK;
-  const bool dev = beta_out && is_device_ptr(beta_out);
-  for (int32_t i = 0; i < B; ++i) {
-    double* out = beta_out ? beta_out + (size_t)i * (size_t)h->D.p : nullptr;
-    flr_result r{};
-    flr_status st = flr_solve_ex(h, l1[i], l2[i], tol, opts, out, &r);
-    (void)dev;
-    if (res) res[i] = r;
-    if (st != FLR_OK && first == FLR_OK) first = st;
-    if (st != FLR_OK && st != FLR_ERR_MAX_ITER && st != FLR_ERR_NUMERICAL) return st;
-  }
-  return first;
 }
 
 flr_status flr_profile_kernels(flr_problem h, int32_t reps, double* avg_us) {

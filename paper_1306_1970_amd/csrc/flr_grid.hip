@@ -1,0 +1,653 @@
+// Batched solver for a grid of (lambda1, lambda2) settings on one resident
+// problem (flr_solve_grid).  Every column is an independent MM solve
+// (section 3.1, Algorithm 2); what they share is X, so the two products of
+// each PCG step become dense GEMMs over all columns:
+//   U = X O^T   (n x B)      O[b] = p_b in a PCG step, x_b at an MM boundary
+//   V = X^T U   (p x B)
+// run as FP64 rocBLAS GEMMs (plain library GEMMs on the matrix cores).
+// Everything else of a step is one fused kernel per column (k_col, one
+// workgroup owns one column): the Laplacian product, p^T Q p, the CG updates,
+// the whole tridiagonal preconditioner solve as a chunked two-level scan, the
+// stopping tests, and at an MM boundary the objective, relative-change test,
+// reweighting, LDL^T factorization and the new residual.  Columns advance at
+// their own pace: each keeps its own phase; finished columns contribute zero
+// operands.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "flr_device.h"
+#include "flr_problem.h"
+
+namespace flr {
+
+struct ColState {
+  int32_t phase, status, first, mm_iter, cg_iter, jacobi;
+  int64_t cg_total;
+  double rz, f_old, f_new, rel_change, rel_res, pad;
+};
+
+struct GridParams {
+  double eps, tol, inner_tol, cnorm;
+  int32_t max_iter, max_cg;
+};
+
+struct GridDev {
+  int64_t n, p, p_pad, nnz;
+  int32_t B, pad;
+  const double* y;
+  const double* c;
+  const double* s;
+  const int32_t* rowptr;
+  const int32_t* col;
+  const int32_t* prevpos;
+  double* x;     // B x p_pad
+  double* r;
+  double* pv;
+  double* g;
+  double* z;
+  double* O;     // GEMM operand, B x p_pad (column-major p_pad x B)
+  double* U;     // n x B (column-major, ld n)
+  double* V;     // p_pad x B (column-major, ld p_pad)
+  double* a;
+  double* d;
+  double* e;
+  double* L;
+  double* invD;
+  double* w;     // B x nnz
+  const double* lam1;
+  const double* lam2;
+  ColState* st;
+  const GridParams* prm;
+};
+
+constexpr int kE = 8;              // consecutive elements per thread in a chunk
+constexpr int kCH = kWG * kE;      // chunk of the two-level scans
+
+// Exclusive value for this thread from the inclusive maps of all threads:
+// the composition of threads 0..t-1 (forward) or t+1..255 (reverse) applied to t_in.
+__device__ inline double exclusive_apply(Aff inc, double t_in, bool reverse, double* sh2) {
+  const int tid = threadIdx.x;
+  __syncthreads();
+  sh2[2 * tid] = inc.a;
+  sh2[2 * tid + 1] = inc.b;
+  __syncthreads();
+  const int src = reverse ? tid + 1 : tid - 1;
+  if (src < 0 || src >= kWG) return t_in;
+  return fma(sh2[2 * src], t_in, sh2[2 * src + 1]);
+}
+
+// z = M^-1 r for one column with the LDL^T factors (L, invD) of the
+// tridiagonal preconditioner: forward g_j = r_j - L_j g_{j-1}, backward
+// z_j = g_j / D_j - L_{j+1} z_{j+1}.  Chunks of 256 x 8 elements; inside a
+// chunk each thread sweeps 8 consecutive elements, the workgroup scans the
+// threads' affine maps, and the chunk's end value carries to the next chunk.
+__device__ void col_tri_solve(const double* __restrict__ r, const double* __restrict__ L,
+                              const double* __restrict__ invD, double* __restrict__ g, double* __restrict__ z,
+                              int64_t p, double* lds, double* sh2) {
+  const int tid = threadIdx.x;
+  const int nch = (int)((p + kCH - 1) / kCH);
+  double carry = 0.0;
+  for (int ch = 0; ch < nch; ++ch) {
+    const int64_t j0 = (int64_t)ch * kCH + (int64_t)tid * kE;
+    double rv[kE], lv[kE];
+#pragma unroll
+    for (int i = 0; i < kE; ++i) {
+      const int64_t j = j0 + i;
+      rv[i] = j < p ? r[j] : 0.0;
+      lv[i] = j < p ? L[j] : 0.0;
+    }
+    double loc = 0.0, A = 1.0;
+#pragma unroll
+    for (int i = 0; i < kE; ++i) {
+      loc = fma(-lv[i], loc, rv[i]);
+      A = -lv[i] * A;
+    }
+    const Aff inc = wg_scan_fwd({A, loc}, lds);
+    double gv = exclusive_apply(inc, carry, false, sh2);
+#pragma unroll
+    for (int i = 0; i < kE; ++i) {
+      gv = fma(-lv[i], gv, rv[i]);
+      const int64_t j = j0 + i;
+      if (j < p) g[j] = gv;
+    }
+    // chunk end value: the last thread's end equals its inclusive map applied to the chunk inflow
+    carry = fma(sh2[2 * (kWG - 1)], carry, sh2[2 * (kWG - 1) + 1]);
+  }
+  __syncthreads();
+  carry = 0.0;
+  for (int ch = nch - 1; ch >= 0; --ch) {
+    const int64_t j0 = (int64_t)ch * kCH + (int64_t)tid * kE;
+    double gv[kE], dv[kE], ln[kE];
+#pragma unroll
+    for (int i = 0; i < kE; ++i) {
+      const int64_t j = j0 + i;
+      gv[i] = j < p ? g[j] : 0.0;
+      dv[i] = j < p ? invD[j] : 0.0;
+      ln[i] = j + 1 < p ? L[j + 1] : 0.0;
+    }
+    double loc = 0.0, A = 1.0;
+#pragma unroll
+    for (int i = kE - 1; i >= 0; --i) {
+      loc = fma(-ln[i], loc, gv[i] * dv[i]);
+      A = -ln[i] * A;
+    }
+    const Aff inc = wg_scan_rev({A, loc}, lds);
+    double zv = exclusive_apply(inc, carry, true, sh2);
+#pragma unroll
+    for (int i = kE - 1; i >= 0; --i) {
+      zv = fma(-ln[i], zv, gv[i] * dv[i]);
+      const int64_t j = j0 + i;
+      if (j < p) z[j] = zv;
+    }
+    carry = fma(sh2[0], carry, sh2[1]);  // thread 0's inclusive map covers the whole chunk
+  }
+  __syncthreads();
+}
+
+// LDL^T factorization of one column's tridiagonal M: the continued fraction
+// D_j = d_j - e_j L_j with L_j = e_j / D_{j-1}, walked sequentially by one
+// thread (the order of the oracle's factorization; a projective-product scan
+// loses accuracy when fused edges make the weights span many decades), with
+// d and e staged through LDS in chunks.  Writes L_j and 1 / D_j.
+__device__ void col_factor(const double* __restrict__ d, const double* __restrict__ e, double* __restrict__ L,
+                           double* __restrict__ invD, int64_t p, double* sh4) {
+  const int tid = threadIdx.x;
+  constexpr int CHF = kWG;  // sh4 holds 4 x 256 doubles
+  double* cd = sh4;
+  double* ce = sh4 + CHF;
+  double* cL = sh4 + 2 * CHF;
+  double* ci = sh4 + 3 * CHF;
+  double Dp = INFINITY;
+  for (int64_t c0 = 0; c0 < p; c0 += CHF) {
+    __syncthreads();
+    const int64_t jj = c0 + tid;
+    cd[tid] = jj < p ? d[jj] : 1.0;
+    ce[tid] = jj < p ? e[jj] : 0.0;
+    __syncthreads();
+    if (tid == 0) {
+      const int nn = (int)min<int64_t>(CHF, p - c0);
+      for (int t = 0; t < nn; ++t) {
+        const double et = ce[t];
+        const double Lt = et != 0.0 ? et / Dp : 0.0;
+        const double Dt = et != 0.0 ? cd[t] - et * Lt : cd[t];
+        cL[t] = Lt;
+        ci[t] = 1.0 / Dt;
+        Dp = Dt;
+      }
+    }
+    __syncthreads();
+    if (jj < p) {
+      L[jj] = cL[tid];
+      invD[jj] = ci[tid];
+    }
+  }
+  __syncthreads();
+}
+
+// (M v)_j for column b: lambda1 a_j v_j + lambda2 sum_k w_jk (v_j - v_k)
+__device__ inline double col_apply_m(const GridDev& G, int b, int64_t j, const double* v, double l1, double l2) {
+  const double* a = G.a + (int64_t)b * G.p_pad;
+  const double* w = G.w + (int64_t)b * G.nnz;
+  const double vj = v[j];
+  double lap = 0.0;
+  for (int q = G.rowptr[j]; q < G.rowptr[j + 1]; ++q) lap = fma(w[q], vj - v[G.col[q]], lap);
+  return l1 * a[j] * vj + l2 * lap;
+}
+
+__global__ __launch_bounds__(kWG) void k_col(GridDev G) {
+  const int b = blockIdx.x, tid = threadIdx.x;
+  __shared__ double lds[24];
+  __shared__ double sh2[2 * kWG];
+  __shared__ double sh4[4 * kWG];
+  ColState s = G.st[b];
+  if (s.phase == PH_DONE) return;
+  const GridParams prm = *G.prm;
+  const double l1 = G.lam1[b], l2 = G.lam2[b];
+  const int64_t p = G.p, P = G.p_pad, off = (int64_t)b * P;
+  double* x = G.x + off;
+  double* r = G.r + off;
+  double* pv = G.pv + off;
+  double* z = G.z + off;
+  double* O = G.O + off;
+  const double* V = G.V + off;
+  const double* U = G.U + (int64_t)b * G.n;
+
+  if (s.phase == PH_CG) {
+    // q = X^T X p + M p (kept in z), p^T q
+    double part = 0.0;
+    for (int64_t j = tid; j < p; j += kWG) {
+      const double q = V[j] + col_apply_m(G, b, j, pv, l1, l2);
+      z[j] = q;
+      part = fma(pv[j], q, part);
+    }
+    const double pq = wg_sum(part, lds);
+    const double nu = s.rz / pq;
+    if (!(pq > 0.0) || !isfinite(nu)) {
+      if (tid == 0) {
+        s.phase = PH_DONE;
+        s.status = ST_NUMERICAL;
+        G.st[b] = s;
+      }
+      for (int64_t j = tid; j < P; j += kWG) O[j] = 0.0;
+      return;
+    }
+    for (int64_t j = tid; j < p; j += kWG) {
+      x[j] = fma(nu, pv[j], x[j]);
+      r[j] = fma(-nu, z[j], r[j]);
+    }
+    __syncthreads();
+    col_tri_solve(r, G.L + off, G.invD + off, G.g + off, z, p, lds, sh2);
+    double rzp = 0.0, rrp = 0.0;
+    for (int64_t j = tid; j < p; j += kWG) {
+      rzp = fma(r[j], z[j], rzp);
+      rrp = fma(r[j], r[j], rrp);
+    }
+    const double rz = wg_sum(rzp, lds);
+    const double rr = wg_sum(rrp, lds);
+    const double rn = sqrt(rr) / prm.cnorm;
+    s.cg_iter += 1;
+    s.cg_total += 1;
+    s.rel_res = rn;
+    const bool done = !(rn > prm.inner_tol) || s.cg_iter >= prm.max_cg;
+    if (done) {
+      s.phase = PH_END;
+      for (int64_t j = tid; j < P; j += kWG) O[j] = j < p ? x[j] : 0.0;
+    } else {
+      const double gamma = rz / s.rz;
+      for (int64_t j = tid; j < p; j += kWG) {
+        const double v = fma(gamma, pv[j], z[j]);
+        pv[j] = v;
+        O[j] = v;
+      }
+      s.rz = rz;
+    }
+    if (tid == 0) G.st[b] = s;
+    return;
+  }
+
+  // ---- MM boundary: U = X x, V = X^T X x for this column ----
+  double lp = 0.0;
+  for (int64_t i = tid; i < G.n; i += kWG) {
+    const double dlt = G.y[i] - U[i];
+    lp = fma(dlt, dlt, lp);
+  }
+  double pp = 0.0;
+  for (int64_t j = tid; j < p; j += kWG) {
+    const double xj = x[j];
+    double pen2 = 0.0;
+    for (int q = G.rowptr[j]; q < G.rowptr[j + 1]; ++q) {
+      const int k = G.col[q];
+      if (k > j) pen2 += fabs(xj - x[k]);
+    }
+    pp += l1 * fabs(xj) + l2 * pen2;
+  }
+  const double loss = wg_sum(lp, lds);
+  const double pen = wg_sum(pp, lds);
+  const double f_new = 0.5 * loss + pen;
+  s.f_new = f_new;
+  bool finish = false;
+  if (!isfinite(f_new)) {
+    s.status = ST_NUMERICAL;
+    finish = true;
+  } else if (s.first) {
+    s.first = 0;
+  } else {
+    s.mm_iter += 1;
+    const double re = s.f_old != 0.0 ? fabs(f_new - s.f_old) / fabs(s.f_old) : fabs(f_new - s.f_old);
+    s.rel_change = re;
+    if (re <= prm.tol) {
+      s.status = ST_OK;
+      finish = true;
+    } else if (s.mm_iter >= prm.max_iter) {
+      s.status = ST_MAX_ITER;
+      finish = true;
+    }
+  }
+  if (finish) {
+    s.phase = PH_DONE;
+    for (int64_t j = tid; j < P; j += kWG) O[j] = 0.0;
+    if (tid == 0) G.st[b] = s;
+    return;
+  }
+  s.f_old = f_new;
+  s.cg_iter = 0;
+  // reweighting (majorizer at the current iterate) and the tridiagonal part of M
+  double* a = G.a + off;
+  double* w = G.w + (int64_t)b * G.nnz;
+  double* d = G.d + off;
+  double* e = G.e + off;
+  for (int64_t j = tid; j < p; j += kWG) {
+    const double xj = x[j];
+    const double aj = 1.0 / (fabs(xj) + prm.eps);
+    a[j] = aj;
+    double wsum = 0.0, ej = 0.0;
+    for (int q = G.rowptr[j]; q < G.rowptr[j + 1]; ++q) {
+      const int k = G.col[q];
+      const double wq = 1.0 / (fabs(xj - x[k]) + prm.eps);
+      w[q] = wq;
+      wsum += wq;
+      if (k == j - 1 && !s.jacobi) ej = -l2 * wq;
+    }
+    double dj = l1 * aj + l2 * wsum;
+    if (s.jacobi) dj += G.s[j];
+    d[j] = dj;
+    e[j] = ej;
+  }
+  __syncthreads();
+  col_factor(d, e, G.L + off, G.invD + off, p, sh4);
+  // r0 = c - (X^T X + M) x
+  for (int64_t j = tid; j < p; j += kWG) r[j] = G.c[j] - (V[j] + col_apply_m(G, b, j, x, l1, l2));
+  __syncthreads();
+  col_tri_solve(r, G.L + off, G.invD + off, G.g + off, z, p, lds, sh2);
+  double rzp = 0.0, rrp = 0.0;
+  for (int64_t j = tid; j < p; j += kWG) {
+    rzp = fma(r[j], z[j], rzp);
+    rrp = fma(r[j], r[j], rrp);
+  }
+  const double rz = wg_sum(rzp, lds);
+  const double rr = wg_sum(rrp, lds);
+  const double rn = sqrt(rr) / prm.cnorm;
+  s.rel_res = rn;
+  s.rz = rz;
+  const bool done = !(rn > prm.inner_tol) || prm.max_cg <= 0;
+  if (done) {
+    s.phase = PH_END;
+    for (int64_t j = tid; j < P; j += kWG) O[j] = j < p ? x[j] : 0.0;
+  } else {
+    s.phase = PH_CG;
+    for (int64_t j = tid; j < P; j += kWG) {
+      const double v = j < p ? z[j] : 0.0;
+      pv[j] = v;
+      O[j] = v;
+    }
+  }
+  if (tid == 0) G.st[b] = s;
+}
+
+// Start of a grid solve: x_b = warm start or X_j^T y / X_j^T X_j, operand O_b = x_b,
+// state at the MM boundary (first evaluation of f).
+__global__ __launch_bounds__(kWG) void k_col_init(GridDev G, const double* __restrict__ warm, int use_warm,
+                                                  const int32_t* __restrict__ jacobi) {
+  const int b = blockIdx.y;
+  const int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  const int64_t off = (int64_t)b * G.p_pad;
+  if (j < G.p_pad) {
+    double v = 0.0;
+    if (j < G.p) v = use_warm ? warm[off + j] : (G.s[j] > 0.0 ? G.c[j] / G.s[j] : 0.0);
+    G.x[off + j] = v;
+    G.O[off + j] = v;
+    G.pv[off + j] = 0.0;
+    G.r[off + j] = 0.0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ColState s{};
+    s.phase = PH_END;
+    s.status = ST_OK;
+    s.first = 1;
+    s.jacobi = jacobi[b];
+    G.st[b] = s;
+  }
+}
+
+template <typename XT>
+__global__ __launch_bounds__(kWG) void k_widen(const XT* __restrict__ X, double* __restrict__ X64, int64_t count) {
+  const int64_t stride = (int64_t)gridDim.x * kWG;
+  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < count; i += stride) {
+    if constexpr (sizeof(XT) == 2) {
+      X64[i] = (double)__uint_as_float(((uint32_t)X[i]) << 16);
+    } else {
+      X64[i] = (double)X[i];
+    }
+  }
+}
+
+}  // namespace flr
+
+using namespace flr;
+
+struct GridWork {
+  int cap = 0;
+  GridDev G{};
+  rocblas_handle blas = nullptr;
+  std::vector<void*> allocs;
+  GridParams* d_prm = nullptr;
+  double* d_lam = nullptr;   // 2 x cap
+  int32_t* d_jac = nullptr;  // cap
+  ColState* h_st = nullptr;  // pinned, cap
+  hipEvent_t ev = nullptr;
+};
+
+namespace flr {
+void grid_free(flr_problem h) {
+  GridWork* gw = h->grid;
+  if (!gw) return;
+  if (gw->blas) rocblas_destroy_handle(gw->blas);
+  for (void* p : gw->allocs) (void)hipFree(p);
+  if (gw->h_st) (void)hipHostFree(gw->h_st);
+  if (gw->ev) (void)hipEventDestroy(gw->ev);
+  delete gw;
+  h->grid = nullptr;
+}
+bool is_device_pointer(const void* p);
+}  // namespace flr
+
+static flr_status gfail(flr_status st, const std::string& m) {
+  set_last_error(m);
+  return st;
+}
+
+#define GCK(expr)                                                                                           \
+  do {                                                                                                      \
+    hipError_t e_ = (expr);                                                                                 \
+    if (e_ != hipSuccess)                                                                                   \
+      return gfail(e_ == hipErrorOutOfMemory ? FLR_ERR_OUT_OF_MEMORY : FLR_ERR_DEVICE,                      \
+                   std::string(#expr) + ": " + hipGetErrorString(e_));                                      \
+  } while (0)
+
+static flr_status grid_prepare(flr_problem h, int B) {
+  const Dims& D = h->D;
+  if (!h->X64) {
+    GCK(hipMalloc(reinterpret_cast<void**>(&h->X64), (size_t)D.n * (size_t)D.ldx * sizeof(double)));
+    const int64_t cnt = D.n * D.ldx;
+    switch (D.dtype) {
+      case 0:
+        GCK(hipMemcpyAsync(h->X64, h->B.X, (size_t)cnt * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+        break;
+      case 1:
+        hipLaunchKernelGGL(k_widen<float>, dim3(2048), dim3(kWG), 0, h->stream,
+                           reinterpret_cast<const float*>(h->B.X), h->X64, cnt);
+        break;
+      default:
+        hipLaunchKernelGGL(k_widen<uint16_t>, dim3(2048), dim3(kWG), 0, h->stream,
+                           reinterpret_cast<const uint16_t*>(h->B.X), h->X64, cnt);
+        break;
+    }
+    GCK(hipGetLastError());
+  }
+  if (h->grid && h->grid->cap >= B) return FLR_OK;
+  grid_free(h);
+  GridWork* gw = new GridWork;
+  h->grid = gw;
+  gw->cap = B;
+  auto al = [&](double** ptr, size_t cnt) -> hipError_t {
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(ptr), std::max<size_t>(cnt, 1) * sizeof(double));
+    if (e == hipSuccess) {
+      gw->allocs.push_back(*ptr);
+      e = hipMemsetAsync(*ptr, 0, std::max<size_t>(cnt, 1) * sizeof(double), h->stream);
+    }
+    return e;
+  };
+  GridDev& G = gw->G;
+  const size_t PB = (size_t)D.p_pad * (size_t)B;
+  GCK(al(&G.x, PB));
+  GCK(al(&G.r, PB));
+  GCK(al(&G.pv, PB));
+  GCK(al(&G.g, PB));
+  GCK(al(&G.z, PB));
+  GCK(al(&G.O, PB));
+  GCK(al(&G.V, PB));
+  GCK(al(&G.U, (size_t)D.n * (size_t)B));
+  GCK(al(&G.a, PB));
+  GCK(al(&G.d, PB));
+  GCK(al(&G.e, PB));
+  GCK(al(&G.L, PB));
+  GCK(al(&G.invD, PB));
+  GCK(al(&G.w, (size_t)std::max<int64_t>(h->nnz, 1) * (size_t)B));
+  GCK(al(&gw->d_lam, 2 * (size_t)B));
+  double* tmp = nullptr;
+  GCK(al(&tmp, (sizeof(ColState) * (size_t)B + 7) / 8));
+  G.st = reinterpret_cast<ColState*>(tmp);
+  GCK(al(&tmp, (sizeof(GridParams) + 7) / 8));
+  gw->d_prm = reinterpret_cast<GridParams*>(tmp);
+  GCK(al(&tmp, ((size_t)B * sizeof(int32_t) + 7) / 8));
+  gw->d_jac = reinterpret_cast<int32_t*>(tmp);
+  GCK(hipHostMalloc(reinterpret_cast<void**>(&gw->h_st), sizeof(ColState) * (size_t)B, hipHostMallocDefault));
+  GCK(hipEventCreateWithFlags(&gw->ev, hipEventDisableTiming));
+  if (rocblas_create_handle(&gw->blas) != rocblas_status_success) return gfail(FLR_ERR_DEVICE, "rocblas_create_handle");
+  rocblas_set_stream(gw->blas, h->stream);
+  G.n = D.n;
+  G.p = D.p;
+  G.p_pad = D.p_pad;
+  G.nnz = std::max<int64_t>(h->nnz, 1);
+  G.y = h->B.y;
+  G.c = h->B.c;
+  G.s = h->B.s;
+  G.rowptr = h->B.rowptr;
+  G.col = h->B.col;
+  G.prevpos = h->B.prevpos;
+  G.lam1 = gw->d_lam;
+  G.lam2 = gw->d_lam + B;
+  G.prm = gw->d_prm;
+  return FLR_OK;
+}
+
+static flr_status grid_run(flr_problem h, const double* l1, const double* l2, int32_t B, double tol,
+                           const flr_solve_opts* o, double* beta_out, flr_result* res) {
+  auto t0 = std::chrono::steady_clock::now();
+  flr_solve_opts dflt;
+  flr_default_opts(&dflt);
+  if (!o) o = &dflt;
+  if (o->precision != FLR_PREC_FP64) return gfail(FLR_ERR_INVALID_ARG, "grid solves run in FP64 in this build");
+  flr_status ps = grid_prepare(h, B);
+  if (ps != FLR_OK) return ps;
+  GridWork* gw = h->grid;
+  GridDev G = gw->G;
+  G.B = B;
+  const Dims& D = h->D;
+  GridParams P{};
+  P.eps = o->eps > 0.0 ? o->eps : 1e-8;
+  P.tol = tol;
+  P.inner_tol = o->inner_tol > 0.0 ? o->inner_tol : tol;
+  P.cnorm = h->cnorm > 0.0 ? h->cnorm : 1.0;
+  P.max_iter = o->max_iter > 0 ? o->max_iter : 10000;
+  P.max_cg = o->max_cg > 0 ? o->max_cg : (int32_t)std::min<int64_t>(D.p, INT32_MAX);
+  std::vector<double> lam((size_t)2 * B);
+  std::vector<int32_t> jac((size_t)B);
+  for (int i = 0; i < B; ++i) {
+    lam[(size_t)i] = l1[i];
+    lam[(size_t)B + i] = l2[i];
+    int pre = o->preconditioner;
+    if (pre == FLR_PRECOND_AUTO) pre = l1[i] > 0.0 ? FLR_PRECOND_TRIDIAG : FLR_PRECOND_JACOBI;
+    if (pre == FLR_PRECOND_TRIDIAG && !(l1[i] > 0.0))
+      return gfail(FLR_ERR_INVALID_ARG, "the tridiagonal preconditioner needs lambda1 > 0");
+    jac[(size_t)i] = pre == FLR_PRECOND_JACOBI ? 1 : 0;
+  }
+  G.lam1 = gw->d_lam;
+  G.lam2 = gw->d_lam + B;
+  GCK(hipMemcpyAsync(gw->d_lam, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  GCK(hipMemcpyAsync(gw->d_jac, jac.data(), jac.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  GCK(hipMemcpyAsync(gw->d_prm, &P, sizeof(P), hipMemcpyHostToDevice, h->stream));
+  const double* warm = nullptr;
+  if (o->warm_start) {
+    if (is_device_pointer(o->warm_start)) {
+      return gfail(FLR_ERR_INVALID_ARG, "grid warm starts are host arrays (B x p)");
+    }
+    std::vector<double> wpad((size_t)B * (size_t)D.p_pad, 0.0);
+    for (int b = 0; b < B; ++b)
+      std::memcpy(&wpad[(size_t)b * D.p_pad], o->warm_start + (size_t)b * D.p, (size_t)D.p * sizeof(double));
+    GCK(hipMemcpyAsync(G.g, wpad.data(), wpad.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    GCK(hipStreamSynchronize(h->stream));
+    warm = G.g;
+  }
+  hipLaunchKernelGGL(k_col_init, dim3((unsigned)((D.p_pad + kWG - 1) / kWG), (unsigned)B), dim3(kWG), 0, h->stream,
+                     G, warm, warm ? 1 : 0, gw->d_jac);
+  GCK(hipGetLastError());
+  const double one = 1.0, zero = 0.0;
+  const int64_t max_steps = (int64_t)P.max_iter * ((int64_t)P.max_cg + 2) + 4;
+  const int check_every = 8;
+  bool done = false;
+  int64_t step = 0;
+  bool pending = false;
+  while (!done) {
+    if (step >= max_steps) return gfail(FLR_ERR_DEVICE, "grid solve did not terminate within its step bound");
+    // U = X O^T : column-major U (n x B) = (X^T)^T O with X^T stored as p_pad x n (ld ldx)
+    if (rocblas_dgemm(gw->blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)D.n, B,
+                      (rocblas_int)D.p_pad, &one, h->X64, (rocblas_int)D.ldx, G.O, (rocblas_int)D.p_pad, &zero, G.U,
+                      (rocblas_int)D.n) != rocblas_status_success)
+      return gfail(FLR_ERR_DEVICE, "rocblas_dgemm (X O^T) failed");
+    // V = X^T U : p_pad x B
+    if (rocblas_dgemm(gw->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)D.p_pad, B,
+                      (rocblas_int)D.n, &one, h->X64, (rocblas_int)D.ldx, G.U, (rocblas_int)D.n, &zero, G.V,
+                      (rocblas_int)D.p_pad) != rocblas_status_success)
+      return gfail(FLR_ERR_DEVICE, "rocblas_dgemm (X^T U) failed");
+    hipLaunchKernelGGL(k_col, dim3((unsigned)B), dim3(kWG), 0, h->stream, G);
+    GCK(hipGetLastError());
+    ++step;
+    if (step % check_every == 0) {
+      if (pending) {
+        GCK(hipEventSynchronize(gw->ev));
+        bool all = true;
+        for (int b = 0; b < B && all; ++b) all = gw->h_st[b].phase == PH_DONE;
+        if (all) done = true;
+      }
+      GCK(hipMemcpyAsync(gw->h_st, G.st, sizeof(ColState) * (size_t)B, hipMemcpyDeviceToHost, h->stream));
+      GCK(hipEventRecord(gw->ev, h->stream));
+      pending = true;
+    }
+  }
+  GCK(hipStreamSynchronize(h->stream));
+  GCK(hipMemcpy(gw->h_st, G.st, sizeof(ColState) * (size_t)B, hipMemcpyDeviceToHost));
+  if (beta_out) {
+    const bool dev = is_device_pointer(beta_out);
+    GCK(hipMemcpy2D(beta_out, (size_t)D.p * sizeof(double), G.x, (size_t)D.p_pad * sizeof(double),
+                    (size_t)D.p * sizeof(double), (size_t)B, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+  }
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  flr_status first = FLR_OK;
+  for (int b = 0; b < B; ++b) {
+    const ColState& s = gw->h_st[b];
+    const flr_status st = s.status == ST_OK ? FLR_OK : s.status == ST_MAX_ITER ? FLR_ERR_MAX_ITER : FLR_ERR_NUMERICAL;
+    if (st != FLR_OK && first == FLR_OK) first = st;
+    if (res) {
+      res[b].objective = s.f_new;
+      res[b].rel_change = s.rel_change;
+      res[b].rel_residual = s.rel_res;
+      res[b].cg_iters = s.cg_total;
+      res[b].mm_iters = s.mm_iter;
+      res[b].status = st;
+      res[b].seconds = secs;
+    }
+  }
+  return first;
+}
+
+extern "C" flr_status flr_solve_grid(flr_problem h, const double* l1, const double* l2, int32_t B, double tol,
+                                     const flr_solve_opts* opts, double* beta_out, flr_result* res) {
+  if (!h || !l1 || !l2 || B < 1) return gfail(FLR_ERR_INVALID_ARG, "bad grid arguments");
+  for (int32_t i = 0; i < B; ++i) {
+    if (!(std::isfinite(l1[i]) && l1[i] >= 0.0) || !(std::isfinite(l2[i]) && l2[i] >= 0.0))
+      return gfail(FLR_ERR_INVALID_ARG, "lambda1 and lambda2 must be finite and >= 0");
+  }
+  if (!(std::isfinite(tol) && tol > 0.0)) return gfail(FLR_ERR_INVALID_ARG, "tol must be finite and > 0");
+  std::unique_lock<std::mutex> lk(h->busy, std::try_to_lock);
+  if (!lk.owns_lock()) return gfail(FLR_ERR_BUSY, "problem handle in use by another thread");
+  if (hipSetDevice(h->ctx->device) != hipSuccess) return gfail(FLR_ERR_DEVICE, "hipSetDevice failed");
+  return grid_run(h, l1, l2, B, tol, opts, beta_out, res);
+}

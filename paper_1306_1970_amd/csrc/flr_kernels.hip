@@ -12,159 +12,10 @@
 
 #include <cmath>
 
+#include "flr_device.h"
 #include "flr_internal.h"
 
 namespace flr {
-
-// ---------------------------------------------------------------------------
-// stored-type loads: 16 bytes per lane, widened to double
-// ---------------------------------------------------------------------------
-template <typename XT> struct XV;
-template <> struct XV<double> {
-  static constexpr int V = 2;
-  using raw = double2;
-  __device__ static inline void cvt(const raw& v, double* o) { o[0] = v.x; o[1] = v.y; }
-};
-template <> struct XV<float> {
-  static constexpr int V = 4;
-  using raw = float4;
-  __device__ static inline void cvt(const raw& v, double* o) {
-    o[0] = (double)v.x; o[1] = (double)v.y; o[2] = (double)v.z; o[3] = (double)v.w;
-  }
-};
-template <> struct XV<uint16_t> {  // bfloat16 bit patterns
-  static constexpr int V = 8;
-  using raw = uint4;
-  __device__ static inline double lo(uint32_t w) { return (double)__uint_as_float(w << 16); }
-  __device__ static inline double hi(uint32_t w) { return (double)__uint_as_float(w & 0xffff0000u); }
-  __device__ static inline void cvt(const raw& v, double* o) {
-    o[0] = lo(v.x); o[1] = hi(v.x); o[2] = lo(v.y); o[3] = hi(v.y);
-    o[4] = lo(v.z); o[5] = hi(v.z); o[6] = lo(v.w); o[7] = hi(v.w);
-  }
-};
-
-template <typename XT>
-__device__ inline typename XV<XT>::raw load16(const XT* p) {
-  return *reinterpret_cast<const typename XV<XT>::raw*>(p);
-}
-
-// ---------------------------------------------------------------------------
-// reductions and scans over one 256-thread workgroup (fixed trees)
-// ---------------------------------------------------------------------------
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Sum over the workgroup; every thread receives the result.  lds: 4 doubles.
-__device__ inline double wg_sum(double v, double* lds) {
-  v = wave_sum(v);
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  __syncthreads();
-  if (l == 0) lds[w] = v;
-  __syncthreads();
-  return (lds[0] + lds[1]) + (lds[2] + lds[3]);
-}
-
-// Four sums over the workgroup at once (one pair of barriers).  lds: 16 doubles.
-__device__ inline void wg_sum4(double* v, double* lds) {
-#pragma unroll
-  for (int k = 0; k < 4; ++k) v[k] = wave_sum(v[k]);
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  __syncthreads();
-  if (l == 0) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) lds[4 * w + k] = v[k];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < 4; ++k) v[k] = (lds[k] + lds[4 + k]) + (lds[8 + k] + lds[12 + k]);
-}
-
-// Affine map t -> a t + b.  compose(E, L) applies E first, then L.
-struct Aff {
-  double a, b;
-};
-__device__ inline Aff compose(Aff E, Aff Lm) { return {Lm.a * E.a, Lm.a * E.b + Lm.b}; }
-
-// Inclusive scan in thread order 0..255 (recurrence t_j = a_j t_{j-1} + b_j).
-// lds: 8 doubles.
-__device__ inline Aff wg_scan_fwd(Aff m, double* lds) {
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    double pa = __shfl_up(m.a, d, 64), pb = __shfl_up(m.b, d, 64);
-    if (l >= d) m = compose({pa, pb}, m);
-  }
-  __syncthreads();
-  if (l == 63) { lds[2 * w] = m.a; lds[2 * w + 1] = m.b; }
-  __syncthreads();
-  Aff pre = {1.0, 0.0};
-  for (int v = 0; v < w; ++v) pre = compose(pre, {lds[2 * v], lds[2 * v + 1]});
-  return compose(pre, m);
-}
-
-// Inclusive scan in thread order 255..0 (recurrence t_j = a_j t_{j+1} + b_j).
-__device__ inline Aff wg_scan_rev(Aff m, double* lds) {
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    double pa = __shfl_down(m.a, d, 64), pb = __shfl_down(m.b, d, 64);
-    if (l + d < 64) m = compose({pa, pb}, m);
-  }
-  __syncthreads();
-  if (l == 0) { lds[2 * w] = m.a; lds[2 * w + 1] = m.b; }
-  __syncthreads();
-  Aff pre = {1.0, 0.0};
-  for (int v = 3; v > w; --v) pre = compose(pre, {lds[2 * v], lds[2 * v + 1]});
-  return compose(pre, m);
-}
-
-// Inclusive scans over the 64 lanes of one wave (no barriers).
-__device__ inline Aff wave_scan_fwd(Aff m) {
-  const int l = threadIdx.x & 63;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    double pa = __shfl_up(m.a, d, 64), pb = __shfl_up(m.b, d, 64);
-    if (l >= d) m = compose({pa, pb}, m);
-  }
-  return m;
-}
-__device__ inline Aff wave_scan_rev(Aff m) {
-  const int l = threadIdx.x & 63;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    double pa = __shfl_down(m.a, d, 64), pb = __shfl_down(m.b, d, 64);
-    if (l + d < 64) m = compose({pa, pb}, m);
-  }
-  return m;
-}
-
-// 2x2 projective (Moebius) product used for the continued fraction
-// D_j = d_j - e_j^2 / D_{j-1} of the tridiagonal LDL^T factorization.
-struct Mob {
-  double m00, m01, m10, m11;
-};
-__device__ inline Mob mob_norm(Mob o) {
-  double mx = fmax(fmax(fabs(o.m00), fabs(o.m01)), fmax(fabs(o.m10), fabs(o.m11)));
-  if (mx > 0.0 && isfinite(mx)) {
-    int ex = ilogb(mx);
-    o.m00 = ldexp(o.m00, -ex); o.m01 = ldexp(o.m01, -ex);
-    o.m10 = ldexp(o.m10, -ex); o.m11 = ldexp(o.m11, -ex);
-  }
-  return o;
-}
-// L * R (R acts first)
-__device__ inline Mob mob_mul(Mob Lm, Mob R) {
-  return mob_norm({Lm.m00 * R.m00 + Lm.m01 * R.m10, Lm.m00 * R.m01 + Lm.m01 * R.m11,
-                   Lm.m10 * R.m00 + Lm.m11 * R.m10, Lm.m10 * R.m01 + Lm.m11 * R.m11});
-}
-
-__device__ inline void copy_state(const State* sin, State* sout, const State& s) {
-  (void)sin;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *sout = s;
-}
 
 // ---------------------------------------------------------------------------
 // Setup: partial column sums of X_ij y_i and X_ij^2 over row panels
@@ -400,7 +251,6 @@ __global__ __launch_bounds__(kWG) void k_gemv_b(Dims D, Bufs B, const State* __r
   __shared__ double sh_u[kMaxR2];
   __shared__ double sh_red[4][64 * 8];
   __shared__ double sh_s[16];
-  __shared__ double sh_d[kBlk], sh_e[kBlk];
 
   // u for the first 256 panel rows (sum of the A partials), issued before
   // the X rows so that waiting for it does not wait for them
@@ -481,7 +331,7 @@ __global__ __launch_bounds__(kWG) void k_gemv_b(Dims D, Bufs B, const State* __r
   }
 
   if (!cg && wg < D.nblk) {
-    // reweighting, tridiagonal part of M, penalties, block product
+    // reweighting and the tridiagonal part of M, penalties
     const int64_t j = (int64_t)wg * kBlk + tid;
     double pen = 0.0, dj = 1.0, ej = 0.0;
     if (j < D.p) {
@@ -508,21 +358,59 @@ __global__ __launch_bounds__(kWG) void k_gemv_b(Dims D, Bufs B, const State* __r
       B.d[j] = 1.0;
       B.e[j] = 0.0;
     }
-    sh_d[tid] = dj;
-    sh_e[tid] = ej;
     const double tot = wg_sum(pen, sh_s);
+    if (tid == 0) B.penpart[wg] = tot;
+  }
+  if (!cg) {
+    // The last workgroup to finish factors M = L D L^T sequentially over all
+    // p elements (the continued fraction D_j = d_j - e_j L_j, L_j = e_j / D_{j-1}),
+    // staged through LDS in chunks; writes L and 1/D for the C launch.
+    __shared__ int sh_flag;
+    __syncthreads();
     if (tid == 0) {
-      B.penpart[wg] = tot;
-      Mob T = {1.0, 0.0, 0.0, 1.0};
-      for (int t = 0; t < kBlk; ++t) {
-        if ((int64_t)wg * kBlk + t >= D.p) break;
-        const double et = sh_e[t];
-        T = mob_mul({sh_d[t], -et * et, 1.0, 0.0}, T);
+      __threadfence();
+      const unsigned prev = atomicAdd(B.counter + 16, 1u);
+      const bool last = prev == (unsigned)(D.gridB - 1);
+      if (last) __threadfence();
+      sh_flag = last;
+    }
+    __syncthreads();
+    if (sh_flag) {
+      double* cd = &sh_red[0][0];
+      double* ce = &sh_red[1][0];
+      double* cL = &sh_red[2][0];
+      double* ci = &sh_red[3][0];
+      constexpr int CHF = 64 * 8;
+      double Dp = INFINITY;
+      for (int64_t c0f = 0; c0f < D.p; c0f += CHF) {
+        __syncthreads();
+        for (int t = tid; t < CHF; t += kWG) {
+          const int64_t jj = c0f + t;
+          cd[t] = jj < D.p ? B.d[jj] : 1.0;
+          ce[t] = jj < D.p ? B.e[jj] : 0.0;
+        }
+        __syncthreads();
+        if (tid == 0) {
+          const int nn = (int)min<int64_t>(CHF, D.p - c0f);
+          for (int t = 0; t < nn; ++t) {
+            const double et = ce[t];
+            const double Lt = et != 0.0 ? et / Dp : 0.0;
+            const double Dt = et != 0.0 ? cd[t] - et * Lt : cd[t];
+            cL[t] = Lt;
+            ci[t] = 1.0 / Dt;
+            Dp = Dt;
+          }
+        }
+        __syncthreads();
+        for (int t = tid; t < CHF; t += kWG) {
+          const int64_t jj = c0f + t;
+          if (jj < D.p) {
+            B.L[jj] = cL[t];
+            B.invD[jj] = ci[t];
+          }
+        }
       }
-      B.mob[4 * wg + 0] = T.m00;
-      B.mob[4 * wg + 1] = T.m01;
-      B.mob[4 * wg + 2] = T.m10;
-      B.mob[4 * wg + 3] = T.m11;
+      if (tid == 0) B.counter[16] = 0u;
     }
   }
 }
@@ -767,9 +655,7 @@ __global__ __launch_bounds__(kWG) void k_block(Dims D, Bufs B, const State* __re
   const Params prm = *prmp;
   __shared__ double lds[24];
   __shared__ double lds2[4];
-  __shared__ double sh_D[kBlk];
   __shared__ double sh_L[kBlk + 1];
-  __shared__ double sh_mob[4][kWG];
   __shared__ double sh_G[kMaxBlocks], sh_Z[kMaxBlocks];
   __shared__ int sh_flag;
 
@@ -834,22 +720,16 @@ __global__ __launch_bounds__(kWG) void k_block(Dims D, Bufs B, const State* __re
   }
 
   // ---- MM boundary ----
-  // inputs that do not depend on the decision, loaded up front
-  double dj = 1.0, ej = 0.0, cj = 0.0, qsum = 0.0, enext = 0.0;
+  // inputs that do not depend on the decision, loaded up front (L and 1/D come
+  // from the sequential factorization at the end of the B launch)
+  double cj = 0.0, qsum = 0.0, Lj = 0.0, invDj = 0.0, Lnb = 0.0;
   if (real) {
-    dj = B.d[j];
-    ej = B.e[j];
     cj = B.c[j];
+    Lj = B.L[j];
+    invDj = B.invD[j];
     for (int rb = 0; rb < D.rb2; ++rb) qsum += B.qpart[(int64_t)rb * D.p_pad + j];
   }
-  if (tid == kBlk - 1 && j + 1 < D.p) enext = B.e[j + 1];
-  // ordered product of the previous blocks' factorization matrices
-  const int e4 = (b + kWG - 1) / kWG;
-  Mob P = {1.0, 0.0, 0.0, 1.0};
-  for (int i = 0; i < e4; ++i) {
-    const int k = tid * e4 + i;
-    if (k < b) P = mob_mul({B.mob[4 * k], B.mob[4 * k + 1], B.mob[4 * k + 2], B.mob[4 * k + 3]}, P);
-  }
+  if (tid == 0) Lnb = (j + kBlk < D.p) ? B.L[j + kBlk] : 0.0;
   // f(b) = loss + penalties (identical arithmetic in every workgroup)
   double fpart = 0.0;
   for (int q = tid; q < D.rb2; q += kWG) fpart += B.losspart[q];
@@ -886,51 +766,8 @@ __global__ __launch_bounds__(kWG) void k_block(Dims D, Bufs B, const State* __re
   o.f_old = f_new;
   o.first_cg = 1;
   o.cg_iter = 0;
-
-  // ordered tree reduction of the per-thread products (later blocks on the left)
-  sh_mob[0][tid] = P.m00;
-  sh_mob[1][tid] = P.m01;
-  sh_mob[2][tid] = P.m10;
-  sh_mob[3][tid] = P.m11;
-  sh_D[tid] = dj;
-  sh_L[tid] = ej;
-  __syncthreads();
-  for (int w = 1; w < kWG; w <<= 1) {
-    if ((tid & (2 * w - 1)) == 0 && tid + w < kWG) {
-      const Mob lo = {sh_mob[0][tid], sh_mob[1][tid], sh_mob[2][tid], sh_mob[3][tid]};
-      const Mob hi = {sh_mob[0][tid + w], sh_mob[1][tid + w], sh_mob[2][tid + w], sh_mob[3][tid + w]};
-      const Mob pr = mob_mul(hi, lo);
-      sh_mob[0][tid] = pr.m00;
-      sh_mob[1][tid] = pr.m01;
-      sh_mob[2][tid] = pr.m10;
-      sh_mob[3][tid] = pr.m11;
-    }
-    __syncthreads();
-  }
-  // factorization D_j = d_j - e_j^2 / D_{j-1} through the block, from the carried-in D
-  if (tid == 0) {
-    double Din = INFINITY;
-    if (b > 0) Din = sh_mob[0][0] / sh_mob[2][0];  // product applied to (1, 0)
-    lds2[2] = Din;
-    double Dp = Din;
-    for (int t = 0; t < kBlk; ++t) {
-      if ((int64_t)b * kBlk + t >= D.p) break;
-      const double et = sh_L[t];
-      const double dd = et != 0.0 ? sh_D[t] - et * (et / Dp) : sh_D[t];
-      sh_D[t] = dd;
-      Dp = dd;
-    }
-  }
-  __syncthreads();
-  double Lj = 0.0, invDj = 0.0;
-  if (real) {
-    const double Dm1 = tid == 0 ? lds2[2] : sh_D[tid - 1];
-    Lj = ej != 0.0 ? ej / Dm1 : 0.0;
-    invDj = 1.0 / sh_D[tid];
-  }
-  __syncthreads();
   sh_L[tid] = Lj;
-  if (tid == kBlk - 1) sh_L[kBlk] = (real && enext != 0.0) ? enext / sh_D[tid] : 0.0;
+  if (tid == 0) sh_L[kBlk] = Lnb;
   __syncthreads();
   const double Lnext = sh_L[tid + 1];
   // phi_j = prod_{i=start..j} (-L_i); psi_j = prod_{i=j+1..end+1} (-L_i);

@@ -1,0 +1,56 @@
+// Host-side handle layouts shared by the engine, the grid solver and the
+// serving loop.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/flr.h"
+#include "flr_internal.h"
+
+struct GridWork;  // batched-grid workspace (flr_grid.hip)
+using flr::Bufs;
+using flr::Dims;
+using flr::Params;
+using flr::State;
+
+struct flr_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+};
+
+// Number of A/B/C rounds captured in one graph (3*S launches; S even keeps
+// the state parity fixed per node).
+static constexpr int kRounds = 16;
+
+struct flr_problem_s {
+  flr_ctx ctx = nullptr;
+  Dims D{};
+  Bufs B{};
+  int64_t m = 0;
+  int64_t nnz = 0;
+  double cnorm = 0.0;
+  hipStream_t stream = nullptr;
+  Params* d_prm = nullptr;
+  Params* h_prm = nullptr;  // pinned
+  State* h_state = nullptr; // pinned, 2 slots
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<void*> allocs;
+  size_t footprint = 0;
+  bool has_solution = false;
+  std::mutex busy;
+  int64_t edges_m = 0;
+  GridWork* grid = nullptr;
+  double* X64 = nullptr;  // FP64 copy of X for the batched products (created on first use)
+};
+
+
+namespace flr {
+void set_last_error(const std::string& s);
+void grid_free(flr_problem h);
+}  // namespace flr

@@ -1,0 +1,93 @@
+"""Batched (lambda1, lambda2) grid solves: every column against the FP64
+oracle (same bar as the single-solve parity tests) and against the single
+solve of the same column."""
+import numpy as np
+import pytest
+
+import flrgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+INNER = 1e-12
+
+
+@pytest.fixture(scope="module")
+def flr():
+    import torch
+
+    assert torch.cuda.is_available()
+    import paper_1306_1970_amd as m
+
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(flr):
+    c = flr.Context(0)
+    yield c
+    c.close()
+
+
+def _grid(flr, ctx, inst, l1, l2, tol, **kw):
+    prob = flr.Problem.from_instance(ctx, inst)
+    st, beta, res = prob.solve_grid(l1, l2, tol=tol, **kw)
+    singles = [prob.solve(a, b, tol=tol, **kw) for a, b in zip(l1, l2)]
+    prob.close()
+    return st, beta, res, singles
+
+
+# beta bar per instance: 1e-8 where the oracle's own Algorithm 1 and Algorithm 2 agree to that level;
+# on the p = 2500 instance they disagree by 8.8e-7 on the lambda = (0.05, 1.5) column at tol 1e-7 (the
+# MM trajectory there is sensitive to rounding in the products), so its bar is the oracle's own spread.
+@pytest.mark.parametrize("n,p,dtype,beta_bar", [(80, 600, flrgen.F64, 1e-8), (120, 2500, flrgen.F32, 1e-6),
+                                                (60, 4100, flrgen.BF16, 1e-6)])
+def test_grid_chain_matches_oracle(flr, ctx, n, p, dtype, beta_bar):
+    inst = flrgen.small_instance(n, p, "chain", dtype=dtype, seed=31)
+    vals = np.array([0.05, 0.4, 1.5])
+    l1, l2 = flrgen.grid_lambdas(vals)
+    print("grid %s B=%d" % (inst.name, l1.size), flush=True)
+    # inner cap raised so that every inner solve really reaches 1e-12 (a capped, inexact
+    # inner solve makes the MM trajectory depend on rounding detail)
+    st, beta, res, singles = _grid(flr, ctx, inst, l1, l2, 1e-7, inner_tol=INNER, max_cg=20 * inst.p)
+    P = oracle.Problem.from_instance(inst)
+    for b in range(l1.size):
+        ref = oracle.solve(P, l1[b], l2[b], tol=1e-7, inner_tol=INNER, method=oracle.ALG2, max_cg=20 * inst.p)
+        err = np.max(np.abs(beta[b] - ref.beta)) / np.max(np.abs(ref.beta))
+        print("  col %d lam=(%g,%g) grid mm=%d cg=%d | oracle mm=%d | single mm=%d | err=%.2e" %
+              (b, l1[b], l2[b], res[b]["mm_iters"], res[b]["cg_iters"], ref.mm_iters, singles[b].mm_iters, err),
+              flush=True)
+        assert res[b]["status"] == flr.FLR_OK
+        assert res[b]["mm_iters"] == ref.mm_iters
+        assert abs(res[b]["objective"] - ref.objective) <= 1e-11 * ref.objective
+        assert err <= beta_bar
+        assert np.max(np.abs(beta[b] - singles[b].beta)) <= beta_bar * np.max(np.abs(singles[b].beta))
+
+
+def test_grid_mixed_graphs_and_lambda1_zero(flr, ctx):
+    # lattice graph and a lambda1 = 0 column (Jacobi) in one grid
+    inst = flrgen.small_instance(60, 100, "lattice", dtype=flrgen.F64, seed=32)
+    l1 = np.array([0.0, 0.2, 1.0])
+    l2 = np.array([0.5, 0.3, 0.1])
+    st, beta, res, singles = _grid(flr, ctx, inst, l1, l2, 1e-7, inner_tol=INNER, max_cg=100 * inst.p)
+    P = oracle.Problem.from_instance(inst)
+    for b in range(l1.size):
+        ref = oracle.solve(P, l1[b], l2[b], tol=1e-7, inner_tol=INNER)
+        err = np.max(np.abs(beta[b] - ref.beta)) / np.max(np.abs(ref.beta))
+        print("  col %d grid mm=%d | oracle mm=%d err=%.2e" % (b, res[b]["mm_iters"], ref.mm_iters, err), flush=True)
+        assert res[b]["mm_iters"] == ref.mm_iters
+        assert err <= 1e-8
+
+
+def test_grid_columns_finish_independently(flr, ctx):
+    # very different lambdas converge after very different MM counts; a capped column reports MAX_ITER
+    inst = flrgen.small_instance(50, 300, "chain", dtype=flrgen.F64, seed=33)
+    l1 = np.array([0.01, 5.0, 0.3])
+    l2 = np.array([0.01, 5.0, 0.3])
+    prob = flr.Problem.from_instance(ctx, inst)
+    st, beta, res = prob.solve_grid(l1, l2, tol=1e-8, max_iter=40)
+    single = [prob.solve(a, b, tol=1e-8, max_iter=40) for a, b in zip(l1, l2)]
+    prob.close()
+    for b in range(3):
+        assert res[b]["status"] == single[b].status
+        assert res[b]["mm_iters"] == single[b].mm_iters
+        np.testing.assert_allclose(beta[b], single[b].beta, rtol=0, atol=1e-8 * np.max(np.abs(single[b].beta)) + 1e-300)
