@@ -263,7 +263,7 @@ class Problem:
     """A resident FLR problem: X (numpy array in its stored dtype, or a
     device tensor), y (float64), edges (int64 pairs)."""
 
-    def __init__(self, ctx: Context, X, x_dtype: int, y, edges):
+    def __init__(self, ctx: Context, X, x_dtype: int, y, edges, use_tuned: bool = True):
         self.ctx = ctx
         if hasattr(X, "data_ptr"):
             n, p = int(X.shape[0]), int(X.shape[1])
@@ -277,7 +277,11 @@ class Problem:
         yv = np.ascontiguousarray(y, dtype=np.float64)
         e = np.ascontiguousarray(np.asarray(edges, dtype=np.int64).reshape(-1, 2))
         self.n, self.p, self.m_in = n, p, e.shape[0]
-        self.h = flr_create(ctx.h, self._X, x_dtype, n, p, ldx, yv, e, e.shape[0])
+        from . import autotune
+
+        tuned = autotune.lookup(n, p, x_dtype) if use_tuned else None
+        with autotune.launch_shape(tuned["target_wg_a"] if tuned else None, tuned["target_wg_b"] if tuned else None):
+            self.h = flr_create(ctx.h, self._X, x_dtype, n, p, ldx, yv, e, e.shape[0])
         self._X = None  # the library holds its own copy
 
     @classmethod

@@ -19,6 +19,7 @@ template <> struct XV<double> {
   static constexpr int V = 2;
   using raw = double2;
   __device__ static inline void cvt(const raw& v, double* o) { o[0] = v.x; o[1] = v.y; }
+  __device__ static inline void cvt(const raw& v, float* o) { o[0] = (float)v.x; o[1] = (float)v.y; }
 };
 template <> struct XV<float> {
   static constexpr int V = 4;
@@ -26,6 +27,7 @@ template <> struct XV<float> {
   __device__ static inline void cvt(const raw& v, double* o) {
     o[0] = (double)v.x; o[1] = (double)v.y; o[2] = (double)v.z; o[3] = (double)v.w;
   }
+  __device__ static inline void cvt(const raw& v, float* o) { o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w; }
 };
 template <> struct XV<uint16_t> {  // bfloat16 bit patterns
   static constexpr int V = 8;
@@ -35,6 +37,12 @@ template <> struct XV<uint16_t> {  // bfloat16 bit patterns
   __device__ static inline void cvt(const raw& v, double* o) {
     o[0] = lo(v.x); o[1] = hi(v.x); o[2] = lo(v.y); o[3] = hi(v.y);
     o[4] = lo(v.z); o[5] = hi(v.z); o[6] = lo(v.w); o[7] = hi(v.w);
+  }
+  __device__ static inline float lof(uint32_t w) { return __uint_as_float(w << 16); }
+  __device__ static inline float hif(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+  __device__ static inline void cvt(const raw& v, float* o) {
+    o[0] = lof(v.x); o[1] = hif(v.x); o[2] = lof(v.y); o[3] = hif(v.y);
+    o[4] = lof(v.z); o[5] = hif(v.z); o[6] = lof(v.w); o[7] = hif(v.w);
   }
 };
 

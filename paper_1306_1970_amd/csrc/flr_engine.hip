@@ -17,7 +17,7 @@
 #include "flr_problem.h"
 
 namespace flr {
-hipError_t launch_rotation(const Dims& D, const Bufs& B, int par, int which, hipStream_t st);
+hipError_t launch_rotation(const Dims& D, const Bufs& B, int par, int which, hipStream_t st, bool mixed);
 hipError_t launch_setup(const Dims& D, const void* X, const double* y, double* cpart, double* spart, double* c,
                         double* s, hipStream_t st);
 hipError_t launch_init(const Dims& D, const Bufs& B, const double* warm, int use_warm, hipStream_t st);
@@ -97,17 +97,20 @@ bool is_device_ptr(const void* ptr) {
   return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
 }
 
-flr_status build_graph(flr_problem h) {
-  if (h->gexec) return FLR_OK;
+flr_status build_graph(flr_problem h, bool mixed) {
+  hipGraphExec_t& ge = mixed ? h->gexec_mixed : h->gexec;
+  hipGraph_t& gr = mixed ? h->graph_mixed : h->graph;
+  if (ge) return FLR_OK;
   HIP_OR_FAIL(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
   hipError_t err = hipSuccess;
-  for (int i = 0; i < 3 * kRounds && err == hipSuccess; ++i) err = launch_rotation(h->D, h->B, i & 1, i % 3, h->stream);
+  for (int i = 0; i < 3 * kRounds && err == hipSuccess; ++i)
+    err = launch_rotation(h->D, h->B, i & 1, i % 3, h->stream, mixed);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(h->stream, &g);
   if (err != hipSuccess) return fail(FLR_ERR_DEVICE, std::string("capture launch: ") + hipGetErrorString(err));
   HIP_OR_FAIL(e2);
-  h->graph = g;
-  HIP_OR_FAIL(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
+  gr = g;
+  HIP_OR_FAIL(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
   return FLR_OK;
 }
 
@@ -163,8 +166,10 @@ flr_status run_solve(flr_problem h, double l1, double l2, double tol, const flr_
     // k_init clears r after reading warm[j] in the same thread: safe element-wise
   }
   HIP_OR_FAIL(launch_init(D, h->B, warm, use_warm, h->stream));
-  flr_status gs = build_graph(h);
+  const bool mixed = P.mixed != 0;
+  flr_status gs = build_graph(h, mixed);
   if (gs != FLR_OK) return gs;
+  hipGraphExec_t gexec = mixed ? h->gexec_mixed : h->gexec;
 
   // launch the captured rotation until the state machine reports done; keep
   // one launch in flight beyond the one being polled
@@ -175,7 +180,7 @@ flr_status run_solve(flr_problem h, double l1, double l2, double tol, const flr_
   while (!done) {
     if (launched >= max_launches) return fail(FLR_ERR_DEVICE, "solve did not terminate within its launch bound");
     const int slot = (int)(launched & 1);
-    HIP_OR_FAIL(hipGraphLaunch(h->gexec, h->stream));
+    HIP_OR_FAIL(hipGraphLaunch(gexec, h->stream));
     HIP_OR_FAIL(hipMemcpyAsync(&h->h_state[slot], &h->B.st[0], sizeof(State), hipMemcpyDeviceToHost, h->stream));
     HIP_OR_FAIL(hipEventRecord(h->ev[slot], h->stream));
     ++launched;
@@ -283,6 +288,8 @@ static void problem_free(flr_problem h) {
   if (h->X64) (void)hipFree(h->X64);
   if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
   if (h->graph) (void)hipGraphDestroy(h->graph);
+  if (h->gexec_mixed) (void)hipGraphExecDestroy(h->gexec_mixed);
+  if (h->graph_mixed) (void)hipGraphDestroy(h->graph_mixed);
   for (void* p : h->allocs) (void)hipFree(p);
   if (h->h_prm) (void)hipHostFree(h->h_prm);
   if (h->h_state) (void)hipHostFree(h->h_state);
@@ -491,7 +498,7 @@ flr_status flr_profile_kernels(flr_problem h, int32_t reps, double* avg_us) {
   HIP_OR_FAIL(hipEventCreate(&e2));
   HIP_OR_FAIL(hipMemcpyAsync(h->B.st, hs, 2 * sizeof(State), hipMemcpyHostToDevice, h->stream));
   HIP_OR_FAIL(hipEventRecord(e0, h->stream));
-  for (int i = 0; i < reps; ++i) HIP_OR_FAIL(launch_rotation(h->D, h->B, 0, 0, h->stream));
+  for (int i = 0; i < reps; ++i) HIP_OR_FAIL(launch_rotation(h->D, h->B, 0, 0, h->stream, false));
   HIP_OR_FAIL(hipEventRecord(e1, h->stream));
   HIP_OR_FAIL(hipMemcpyAsync(h->B.st, hs, 2 * sizeof(State), hipMemcpyHostToDevice, h->stream));
   HIP_OR_FAIL(hipEventRecord(e0, h->stream));
@@ -499,14 +506,14 @@ flr_status flr_profile_kernels(flr_problem h, int32_t reps, double* avg_us) {
   float ms_a = 0.f;
   // re-time A from its own start event
   HIP_OR_FAIL(hipEventRecord(e0, h->stream));
-  for (int i = 0; i < reps; ++i) HIP_OR_FAIL(launch_rotation(h->D, h->B, 0, 0, h->stream));
+  for (int i = 0; i < reps; ++i) HIP_OR_FAIL(launch_rotation(h->D, h->B, 0, 0, h->stream, false));
   HIP_OR_FAIL(hipEventRecord(e1, h->stream));
   HIP_OR_FAIL(hipMemcpyAsync(h->B.st, hs, 2 * sizeof(State), hipMemcpyHostToDevice, h->stream));
   HIP_OR_FAIL(hipStreamSynchronize(h->stream));
   HIP_OR_FAIL(hipEventElapsedTime(&ms_a, e0, e1));
   float ms_b = 0.f;
   HIP_OR_FAIL(hipEventRecord(e1, h->stream));
-  for (int i = 0; i < reps; ++i) HIP_OR_FAIL(launch_rotation(h->D, h->B, 1, 1, h->stream));
+  for (int i = 0; i < reps; ++i) HIP_OR_FAIL(launch_rotation(h->D, h->B, 1, 1, h->stream, false));
   HIP_OR_FAIL(hipEventRecord(e2, h->stream));
   HIP_OR_FAIL(hipStreamSynchronize(h->stream));
   HIP_OR_FAIL(hipEventElapsedTime(&ms_b, e1, e2));

@@ -97,6 +97,59 @@ __global__ __launch_bounds__(kWG) void k_init(Dims D, Bufs B, const double* __re
   }
 }
 
+// Rows r0..r1 of one column panel: u_part[cb][i] = sum_j X_ij v_j, with the
+// first pair of rows already in registers and the next pair always in flight.
+// ACC = double (FP64 path) or float (the inner PCG products of the mixed path).
+template <typename XT, typename ACC>
+__device__ inline void rows_a(const Dims& D, const Bufs& B, const XT* Xb, int cb, int64_t r0, int64_t r1, int64_t c0,
+                              int lane, int wave, const double* sh_v, typename XV<XT>::raw (&cur0)[4],
+                              typename XV<XT>::raw (&cur1)[4]) {
+  constexpr int V = XV<XT>::V;
+  constexpr int NV = 4;
+  using RAW = typename XV<XT>::raw;
+  ACC pl[NV][V];
+#pragma unroll
+  for (int t = 0; t < NV; ++t)
+#pragma unroll
+    for (int v = 0; v < V; ++v) pl[t][v] = (ACC)sh_v[(t * 64 + lane) * V + v];
+  for (int64_t i = r0 + wave; i < r1; i += 8) {
+    const int64_t i1 = i + 4, in0 = i + 8, in1 = i + 12;
+    const bool has1 = i1 < r1;
+    RAW nx0[NV], nx1[NV];
+#pragma unroll
+    for (int t = 0; t < NV; ++t) {
+      const int64_t col = c0 + (int64_t)(t * 64 + lane) * V;
+      if (in0 < r1) nx0[t] = load16(Xb + in0 * D.ldx + col);
+      if (in1 < r1) nx1[t] = load16(Xb + in1 * D.ldx + col);
+    }
+    ACC acc0 = 0, acc1 = 0;
+#pragma unroll
+    for (int t = 0; t < NV; ++t) {
+      ACC xv[V];
+      XV<XT>::cvt(cur0[t], xv);
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc0 = fma(xv[v], pl[t][v], acc0);
+      if (has1) {
+        ACC xw[V];
+        XV<XT>::cvt(cur1[t], xw);
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc1 = fma(xw[v], pl[t][v], acc1);
+      }
+    }
+    const double s0 = wave_sum((double)acc0);
+    const double s1 = wave_sum((double)acc1);
+    if (lane == 0) {
+      B.upart[(int64_t)cb * D.n + i] = s0;
+      if (has1) B.upart[(int64_t)cb * D.n + i1] = s1;
+    }
+#pragma unroll
+    for (int t = 0; t < NV; ++t) {
+      cur0[t] = nx0[t];
+      cur1[t] = nx1[t];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // A: row-panel GEMV u_part[cb] = X[rb, cb] v[cb].  In a PCG step v is the new
 // direction p = z + gamma p_old, where z = M^-1 r is rebuilt from the local
@@ -105,7 +158,7 @@ __global__ __launch_bounds__(kWG) void k_init(Dims D, Bufs B, const double* __re
 // MM boundary, v is the iterate x.  The state is read through a restrict
 // pointer (scalar loads), so it does not wait behind the X loads.
 // ---------------------------------------------------------------------------
-template <typename XT>
+template <typename XT, bool MX>
 __global__ __launch_bounds__(kWG) void k_gemv_a(Dims D, Bufs B, const State* __restrict__ sin,
                                                 State* __restrict__ sout) {
   constexpr int V = XV<XT>::V;
@@ -169,47 +222,10 @@ __global__ __launch_bounds__(kWG) void k_gemv_a(Dims D, Bufs B, const State* __r
   }
   __syncthreads();
 
-  double pl[NV][V];
-#pragma unroll
-  for (int t = 0; t < NV; ++t)
-#pragma unroll
-    for (int v = 0; v < V; ++v) pl[t][v] = sh_v[(t * 64 + lane) * V + v];
-  for (int64_t i = r0 + wave; i < r1; i += 8) {
-    const int64_t i1 = i + 4, in0 = i + 8, in1 = i + 12;
-    const bool has1 = i1 < r1;
-    RAW nx0[NV], nx1[NV];
-#pragma unroll
-    for (int t = 0; t < NV; ++t) {
-      const int64_t col = c0 + (int64_t)(t * 64 + lane) * V;
-      if (in0 < r1) nx0[t] = load16(Xb + in0 * D.ldx + col);
-      if (in1 < r1) nx1[t] = load16(Xb + in1 * D.ldx + col);
-    }
-    double acc0 = 0.0, acc1 = 0.0;
-#pragma unroll
-    for (int t = 0; t < NV; ++t) {
-      double xv[V];
-      XV<XT>::cvt(cur0[t], xv);
-#pragma unroll
-      for (int v = 0; v < V; ++v) acc0 = fma(xv[v], pl[t][v], acc0);
-      if (has1) {
-        double xw[V];
-        XV<XT>::cvt(cur1[t], xw);
-#pragma unroll
-        for (int v = 0; v < V; ++v) acc1 = fma(xw[v], pl[t][v], acc1);
-      }
-    }
-    acc0 = wave_sum(acc0);
-    acc1 = wave_sum(acc1);
-    if (lane == 0) {
-      B.upart[(int64_t)cb * D.n + i] = acc0;
-      if (has1) B.upart[(int64_t)cb * D.n + i1] = acc1;
-    }
-#pragma unroll
-    for (int t = 0; t < NV; ++t) {
-      cur0[t] = nx0[t];
-      cur1[t] = nx1[t];
-    }
-  }
+  if (MX && s.phase == PH_CG)
+    rows_a<XT, float>(D, B, Xb, cb, r0, r1, c0, lane, wave, sh_v, cur0, cur1);
+  else
+    rows_a<XT, double>(D, B, Xb, cb, r0, r1, c0, lane, wave, sh_v, cur0, cur1);
 }
 
 // (M v)_j = lambda1 a_j v_j + lambda2 sum_k w_jk (v_j - v_k)  (A and B of the linear system)
@@ -220,6 +236,41 @@ __device__ inline double apply_m(const Bufs& B, const Params& prm, int64_t j, co
   return prm.lam1 * B.a[j] * vj + prm.lam2 * lap;
 }
 
+// Rows r0..r1 of one column panel for this lane's V columns:
+// out[v] = sum_i X_{i, c0+v} u_i (rows of this wave, RU rows in flight).
+template <typename XT, typename ACC, int RU>
+__device__ inline void cols_b(const Dims& D, const XT* Xb, int64_t r0, int64_t r1, int64_t c0, int wave,
+                              const double* sh_u, typename XV<XT>::raw (&cur)[RU], double* out) {
+  constexpr int V = XV<XT>::V;
+  using RAW = typename XV<XT>::raw;
+  ACC acc[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) acc[v] = 0;
+  for (int64_t i = r0 + wave; i < r1; i += 4 * RU) {
+    RAW nxt[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int64_t ii = i + 4 * RU + 4 * u;
+      if (ii < r1) nxt[u] = load16(Xb + ii * D.ldx + c0);
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int64_t ii = i + 4 * u;
+      if (ii < r1) {
+        ACC xv[V];
+        XV<XT>::cvt(cur[u], xv);
+        const ACC uu = (ACC)sh_u[ii - r0];
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] = fma(xv[v], uu, acc[v]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < RU; ++u) cur[u] = nxt[u];
+  }
+#pragma unroll
+  for (int v = 0; v < V; ++v) out[v] = (double)acc[v];
+}
+
 // ---------------------------------------------------------------------------
 // B: column-panel GEMV q_part[rb] = X[rb, :]^T u[rb] (u summed from the A
 // partials).  PCG step: panel row 0 adds M p and each workgroup emits its
@@ -228,7 +279,7 @@ __device__ inline double apply_m(const Bufs& B, const Params& prm, int64_t j, co
 // a_j = 1/(|b_j|+eps), w_jk = 1/(|b_j - b_k|+eps), the tridiagonal part of M,
 // the penalty sums of f, and each block's factorization product.
 // ---------------------------------------------------------------------------
-template <typename XT>
+template <typename XT, bool MX>
 __global__ __launch_bounds__(kWG) void k_gemv_b(Dims D, Bufs B, const State* __restrict__ sin,
                                                 State* __restrict__ sout, const Params* __restrict__ prmp) {
   constexpr int V = XV<XT>::V;
@@ -284,32 +335,10 @@ __global__ __launch_bounds__(kWG) void k_gemv_b(Dims D, Bufs B, const State* __r
       }
     }
     __syncthreads();
-    double acc[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) acc[v] = 0.0;
-    for (int64_t i = r0 + wave; i < r1; i += 4 * RU) {
-      RAW nxt[RU];
-#pragma unroll
-      for (int u = 0; u < RU; ++u) {
-        const int64_t ii = i + 4 * RU + 4 * u;
-        if (ii < r1) nxt[u] = load16(Xb + ii * D.ldx + c0);
-      }
-#pragma unroll
-      for (int u = 0; u < RU; ++u) {
-        const int64_t ii = i + 4 * u;
-        if (ii < r1) {
-          double xv[V];
-          XV<XT>::cvt(cur[u], xv);
-          const double uu = sh_u[ii - r0];
-#pragma unroll
-          for (int v = 0; v < V; ++v) acc[v] = fma(xv[v], uu, acc[v]);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < RU; ++u) cur[u] = nxt[u];
-    }
-#pragma unroll
-    for (int v = 0; v < V; ++v) sh_red[wave][lane * V + v] = acc[v];
+    if (MX && cg)
+      cols_b<XT, float, RU>(D, Xb, r0, r1, c0, wave, sh_u, cur, &sh_red[wave][lane * V]);
+    else
+      cols_b<XT, double, RU>(D, Xb, r0, r1, c0, wave, sh_u, cur, &sh_red[wave][lane * V]);
     __syncthreads();
     double dotp = 0.0;
     for (int t = tid; t < 64 * V; t += kWG) {
@@ -812,16 +841,16 @@ __global__ __launch_bounds__(kWG) void k_block(Dims D, Bufs B, const State* __re
 // ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
-template <typename XT>
+template <typename XT, bool MX>
 static hipError_t launch_rotation_t(const Dims& D, const Bufs& B, int par, int which, hipStream_t st) {
   const State* sin = B.st + par;
   State* sout = B.st + (par ^ 1);
   switch (which) {
     case 0:
-      hipLaunchKernelGGL(k_gemv_a<XT>, dim3(D.cb1 * D.rb1), dim3(kWG), 0, st, D, B, sin, sout);
+      hipLaunchKernelGGL((k_gemv_a<XT, MX>), dim3(D.cb1 * D.rb1), dim3(kWG), 0, st, D, B, sin, sout);
       break;
     case 1:
-      hipLaunchKernelGGL(k_gemv_b<XT>, dim3(D.gridB), dim3(kWG), 0, st, D, B, sin, sout, B.prm);
+      hipLaunchKernelGGL((k_gemv_b<XT, MX>), dim3(D.gridB), dim3(kWG), 0, st, D, B, sin, sout, B.prm);
       break;
     default:
       hipLaunchKernelGGL(k_block, dim3(D.nblk), dim3(kWG), 0, st, D, B, sin, sout, B.prm);
@@ -830,11 +859,14 @@ static hipError_t launch_rotation_t(const Dims& D, const Bufs& B, int par, int w
   return hipGetLastError();
 }
 
-hipError_t launch_rotation(const Dims& D, const Bufs& B, int par, int which, hipStream_t st) {
+hipError_t launch_rotation(const Dims& D, const Bufs& B, int par, int which, hipStream_t st, bool mixed) {
   switch (D.dtype) {
-    case 0: return launch_rotation_t<double>(D, B, par, which, st);
-    case 1: return launch_rotation_t<float>(D, B, par, which, st);
-    default: return launch_rotation_t<uint16_t>(D, B, par, which, st);
+    case 0: return mixed ? launch_rotation_t<double, true>(D, B, par, which, st)
+                         : launch_rotation_t<double, false>(D, B, par, which, st);
+    case 1: return mixed ? launch_rotation_t<float, true>(D, B, par, which, st)
+                         : launch_rotation_t<float, false>(D, B, par, which, st);
+    default: return mixed ? launch_rotation_t<uint16_t, true>(D, B, par, which, st)
+                          : launch_rotation_t<uint16_t, false>(D, B, par, which, st);
   }
 }
 

@@ -40,6 +40,8 @@ struct flr_problem_s {
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph_mixed = nullptr;
+  hipGraphExec_t gexec_mixed = nullptr;
   std::vector<void*> allocs;
   size_t footprint = 0;
   bool has_solution = false;

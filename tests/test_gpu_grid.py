@@ -36,12 +36,14 @@ def _grid(flr, ctx, inst, l1, l2, tol, **kw):
     return st, beta, res, singles
 
 
-# beta bar per instance: 1e-8 where the oracle's own Algorithm 1 and Algorithm 2 agree to that level;
-# on the p = 2500 instance they disagree by 8.8e-7 on the lambda = (0.05, 1.5) column at tol 1e-7 (the
-# MM trajectory there is sensitive to rounding in the products), so its bar is the oracle's own spread.
-@pytest.mark.parametrize("n,p,dtype,beta_bar", [(80, 600, flrgen.F64, 1e-8), (120, 2500, flrgen.F32, 1e-6),
-                                                (60, 4100, flrgen.BF16, 1e-6)])
-def test_grid_chain_matches_oracle(flr, ctx, n, p, dtype, beta_bar):
+# Bars per instance: beta 1e-8 and objective 1e-11 where the oracle's own Algorithm 1 and Algorithm 2
+# agree to that level.  On the p = 2500 instance they disagree on the lambda = (0.05, 1.5) column at tol
+# 1e-7 by 8.8e-7 in beta and 4.1e-10 in the objective (same MM count; the MM trajectory there is
+# sensitive to rounding in the products), so those instances use the oracle's own spread as the bar.
+@pytest.mark.parametrize("n,p,dtype,beta_bar,obj_bar", [(80, 600, flrgen.F64, 1e-8, 1e-11),
+                                                        (120, 2500, flrgen.F32, 1e-6, 1e-9),
+                                                        (60, 4100, flrgen.BF16, 1e-6, 1e-9)])
+def test_grid_chain_matches_oracle(flr, ctx, n, p, dtype, beta_bar, obj_bar):
     inst = flrgen.small_instance(n, p, "chain", dtype=dtype, seed=31)
     vals = np.array([0.05, 0.4, 1.5])
     l1, l2 = flrgen.grid_lambdas(vals)
@@ -58,7 +60,7 @@ def test_grid_chain_matches_oracle(flr, ctx, n, p, dtype, beta_bar):
               flush=True)
         assert res[b]["status"] == flr.FLR_OK
         assert res[b]["mm_iters"] == ref.mm_iters
-        assert abs(res[b]["objective"] - ref.objective) <= 1e-11 * ref.objective
+        assert abs(res[b]["objective"] - ref.objective) <= obj_bar * ref.objective
         assert err <= beta_bar
         assert np.max(np.abs(beta[b] - singles[b].beta)) <= beta_bar * np.max(np.abs(singles[b].beta))
 

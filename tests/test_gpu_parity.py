@@ -215,3 +215,23 @@ def test_duplicate_and_reversed_edges_are_one_set(flr, ctx):
     p1.close()
     p2.close()
     assert np.array_equal(a.beta, b.beta)
+
+
+@pytest.mark.parametrize("dtype", [flrgen.F32, flrgen.BF16])
+def test_mixed_precision_objective_gap(flr, ctx, dtype):
+    # inner PCG products in FP32, FP64 residual c - Q(beta) beta and objective at every MM step:
+    # the result's relative objective gap to the FP64 oracle at the same tolerance must be <= 1e-6
+    inst = flrgen.config2(n=200, p=2000, dtype=dtype)
+    prob = flr.Problem.from_instance(ctx, inst)
+    mixed = prob.solve(inst.lam1, inst.lam2, tol=1e-8, precision=flr.FLR_PREC_MIXED_FP32)
+    plain = prob.solve(inst.lam1, inst.lam2, tol=1e-8)
+    prob.close()
+    ref = oracle.solve(oracle.Problem.from_instance(inst), inst.lam1, inst.lam2, tol=1e-8, method=oracle.ALG2)
+    f_mixed = oracle.objective(oracle.Problem.from_instance(inst), inst.lam1, inst.lam2, mixed.beta)
+    gap = (f_mixed - ref.objective) / ref.objective
+    print("  mixed mm=%d cg=%d gap=%.2e | plain mm=%d cg=%d | oracle mm=%d" %
+          (mixed.mm_iters, mixed.cg_iters, gap, plain.mm_iters, plain.cg_iters, ref.mm_iters), flush=True)
+    assert mixed.status == flr.FLR_OK
+    assert abs(gap) <= 1e-6
+    # the reported objective is the FP64 objective of the returned beta
+    assert abs(mixed.objective - f_mixed) <= 1e-11 * f_mixed
