@@ -13,6 +13,11 @@ Workloads (--workload):
       (the configuration the headline metric is quoted on; default)
   c1  n=100, p=500, FP64 X (small case)
   c4  n=5000, p=50000, X stored BF16, y FP32
+  c5  serving stream: Poisson arrivals of mixed requests (p in {1k, 5k, 10k,
+      50k}, n = p/5, chain / lattice / all-pairs graphs, (lambda1, lambda2)
+      log-uniform in [0.01, 10]) through the continuous-batching server, with
+      HBM-footprint admission and warm starts; reports p50 / p99 latency and
+      solves/s (a separate line, not the headline)
 """
 from __future__ import annotations
 
@@ -88,7 +93,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4", "c5"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-mm-sample", type=int, default=4)
@@ -97,6 +102,13 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="after the solves, copy this many MiB with a plain device copy 3 times (reference "
                          "dispatches for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-rate", type=float, default=8.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-slots", type=int, default=4, help="concurrent solves (worker slots)")
+    ap.add_argument("--serve-instances", type=int, default=1, help="resident problems per (p, graph) cell")
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serve-ps", default="1000,5000,10000,50000")
+    ap.add_argument("--serve-tol", type=float, default=1e-6)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported (the multi-GPU layout is "
@@ -109,6 +121,8 @@ def main():
     import paper_1306_1970_amd as flr
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "c5":
+        return serve_main(args, flr)
     inst, wname = make_workload(args.workload)
     print("bench: workload %s n=%d p=%d m=%d dtype=%s" % (wname, inst.n, inst.p, inst.m, inst.dtype),
           file=sys.stderr, flush=True)
@@ -184,6 +198,86 @@ def main():
         line["calibration_copy_bytes"] = nb
     prob.close()
     ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+def serve_main(args, flr):
+    """Serving stream: the arrivals are replayed in real time by a submitter
+    thread; latency is submit-to-result as the server measures it."""
+    import threading
+
+    import numpy as np
+
+    import flrgen
+
+    ps = tuple(int(x) for x in args.serve_ps.split(","))
+    reqs = flrgen.serving_requests(args.serve_requests, seed=5, rate=args.serve_rate, ps=ps)
+    ctx = flr.Context(0)
+    cells = {}
+    t_setup = time.perf_counter()
+    for r in reqs:
+        key = (r["p"], r["graph"], r["slot"] % args.serve_instances)
+        if key not in cells:
+            inst = flrgen.serving_cell(r["p"], r["graph"], seed=1000 + len(cells))
+            cells[key] = flr.Problem.from_instance(ctx, inst)
+            print("bench: resident %s n=%d p=%d m=%d footprint %.1f MiB" % (inst.name, inst.n, inst.p, inst.m,
+                  cells[key].footprint / 2 ** 20), file=sys.stderr, flush=True)
+            del inst
+    print("bench: %d resident problems in %.1f s" % (len(cells), time.perf_counter() - t_setup), file=sys.stderr,
+          flush=True)
+    budget = int(args.serve_budget_gib * 2 ** 30)
+    srv = flr.flr_server_create(ctx.h, budget, args.serve_slots)
+    opts = flr.default_opts(use_last=1)
+    tickets = [None] * len(reqs)
+    t0 = time.perf_counter()
+
+    def submitter():
+        for i, r in enumerate(reqs):
+            wait = t0 + r["t"] - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            h = cells[(r["p"], r["graph"], r["slot"] % args.serve_instances)].h
+            tickets[i] = flr.flr_server_submit(srv, h, r["lam1"], r["lam2"], args.serve_tol, opts)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    th.join()
+    lat, mm, cg, status = [], 0, 0, {}
+    for i, t in enumerate(tickets):
+        st, res = flr.flr_server_poll(srv, t, True)
+        lat.append(res.seconds)
+        mm += res.mm_iters
+        cg += res.cg_iters
+        status[st] = status.get(st, 0) + 1
+        if (i + 1) % 16 == 0:
+            print("bench: %d/%d done, %.1f s" % (i + 1, len(tickets), time.perf_counter() - t0), file=sys.stderr,
+                  flush=True)
+    elapsed = time.perf_counter() - t0
+    flr.flr_server_destroy(srv)
+    for p in cells.values():
+        p.close()
+    ctx.close()
+    lat = np.array(lat)
+    line = {
+        "metric": "FLR serving: solves/s with p50/p99 latency (Poisson arrivals, mixed p and graphs)",
+        "value": len(reqs) / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": len(reqs),
+        "warmup": 0,
+        "ms_per_step": 1000.0 * elapsed / len(reqs),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "c5_serving_mixed_p%s" % "-".join(str(p) for p in ps), "requests": len(reqs),
+                   "arrival_rate_per_s": args.serve_rate, "slots": args.serve_slots,
+                   "resident_problems": len(cells), "budget_bytes": budget, "tol": args.serve_tol,
+                   "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+                   "max_s": float(lat.max()), "mm_iters": mm, "cg_iters": cg,
+                   "status_counts": {str(k): v for k, v in status.items()}},
+    }
     print(json.dumps(line), flush=True)
 
 
