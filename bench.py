@@ -13,6 +13,11 @@ Workloads (--workload):
       (the configuration the headline metric is quoted on; default)
   c1  n=100, p=500, FP64 X (small case)
   c4  n=5000, p=50000, X stored BF16, y FP32
+  c3  batched grid: two-dimensional FLR on the 100 x 100 lattice, n=2000,
+      X FP32, the 16 x 16 log-spaced (lambda1, lambda2) grid over [0.01, 10]
+      solved in one batched solve (FP64 GEMMs for X O and X^T U); a sample of
+      the same columns through the plain single-solve path gives the plain
+      solves/s beside it (a separate line, not the headline)
   c5  serving stream: Poisson arrivals of mixed requests (p in {1k, 5k, 10k,
       50k}, n = p/5, chain / lattice / all-pairs graphs, (lambda1, lambda2)
       log-uniform in [0.01, 10]) through the continuous-batching server, with
@@ -93,7 +98,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-mm-sample", type=int, default=4)
@@ -102,6 +107,9 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="after the solves, copy this many MiB with a plain device copy 3 times (reference "
                          "dispatches for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--grid-side", type=int, default=16, help="c3: lambda values per axis (side^2 columns)")
+    ap.add_argument("--grid-tol", type=float, default=1e-6, help="c3: relative objective change tolerance")
+    ap.add_argument("--plain-sample", type=int, default=2, help="c3: columns also solved by the plain path")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-rate", type=float, default=8.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-slots", type=int, default=4, help="concurrent solves (worker slots)")
@@ -123,6 +131,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "c5":
         return serve_main(args, flr)
+    if args.workload == "c3":
+        return grid_main(args, flr)
     inst, wname = make_workload(args.workload)
     print("bench: workload %s n=%d p=%d m=%d dtype=%s" % (wname, inst.n, inst.p, inst.m, inst.dtype),
           file=sys.stderr, flush=True)
@@ -198,6 +208,74 @@ def main():
         line["calibration_copy_bytes"] = nb
     prob.close()
     ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+def grid_main(args, flr):
+    """Batched lambda grid against the plain path on the same GPU."""
+    import numpy as np
+
+    import flrgen
+
+    inst = flrgen.config3()
+    vals = np.logspace(-2.0, 1.0, args.grid_side)
+    l1, l2 = flrgen.grid_lambdas(vals)
+    B = int(l1.size)
+    print("bench: workload %s n=%d p=%d m=%d B=%d" % (inst.name, inst.n, inst.p, inst.m, B), file=sys.stderr,
+          flush=True)
+    ctx = flr.Context(0)
+    prob = flr.Problem.from_instance(ctx, inst)
+    # warm-up: one capped batched step prepares the FP64 copy of X, the
+    # workspace for B columns and the GEMM handles
+    prob.solve_grid(l1, l2, tol=1e-2, max_iter=1, max_cg=2)
+    t0 = time.perf_counter()
+    st, beta, res = prob.solve_grid(l1, l2, tol=args.grid_tol)
+    t_grid = time.perf_counter() - t0
+    print("bench: grid of %d columns %.2f s, status %d, mm %d..%d, cg %d..%d" % (
+        B, t_grid, st, min(r["mm_iters"] for r in res), max(r["mm_iters"] for r in res),
+        min(r["cg_iters"] for r in res), max(r["cg_iters"] for r in res)), file=sys.stderr, flush=True)
+    # plain path on a sample of the same columns (spread over the grid)
+    pick = np.linspace(0, B - 1, max(1, args.plain_sample)).round().astype(int)
+    t_plain, gaps = 0.0, []
+    for b in pick:
+        t1 = time.perf_counter()
+        s1 = prob.solve(l1[b], l2[b], tol=args.grid_tol)
+        t_plain += time.perf_counter() - t1
+        gaps.append(abs(s1.objective - res[b]["objective"]) / abs(s1.objective))
+        print("bench: plain column %d lam=(%.3g,%.3g) %.2f s mm %d cg %d | grid mm %d cg %d | obj gap %.2e" % (
+            b, l1[b], l2[b], time.perf_counter() - t1, s1.mm_iters, s1.cg_iters, res[b]["mm_iters"],
+            res[b]["cg_iters"], gaps[-1]), file=sys.stderr, flush=True)
+    plain_rate = len(pick) / t_plain
+    grid_rate = B / t_grid
+    ua, va = flr.flr_profile_grid(prob.h, B, 20)
+    flops = 2.0 * inst.n * inst.p * B  # one GEMM
+    dom_us = max(ua, va)
+    achieved = flops / (dom_us * 1e-6) / 1e12
+    prob.close()
+    ctx.close()
+    line = {
+        "metric": "FLR batched lambda-grid solves/s vs plain path (same GPU)",
+        "value": grid_rate,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": 1000.0 * t_grid,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "c3_lattice_q100_n2000_f32_grid%dx%d" % (args.grid_side, args.grid_side),
+                   "n": inst.n, "p": inst.p, "columns": B, "tol": args.grid_tol,
+                   "plain_solves_per_s": plain_rate, "plain_sample_columns": [int(b) for b in pick],
+                   "speedup_vs_plain": grid_rate / plain_rate, "max_objective_gap_vs_plain": max(gaps),
+                   "status": int(st), "mm_iters_max": max(r["mm_iters"] for r in res),
+                   "cg_iters_max": max(r["cg_iters"] for r in res)},
+        "roofline": {"bound": "mfma", "kernel": "dgemm_XO" if ua >= va else "dgemm_XtU", "achieved": achieved,
+                     "peak": 78.6, "unit": "TFLOP/s", "frac": achieved / 78.6, "traffic": None,
+                     "avg_us": dom_us, "algorithmic_flops": flops, "other_kernel_us": min(ua, va)},
+    }
     print(json.dumps(line), flush=True)
 
 

@@ -157,6 +157,14 @@ void flr_server_destroy(flr_server s);
  * solution is left intact.  Needs a completed solve on the handle. */
 flr_status flr_profile_kernels(flr_problem h, int32_t reps, double* avg_us);
 
+/* Profiling of the batched products of flr_solve_grid: run the two FP64 GEMMs
+ * of one batched PCG step, U = X O (n x B) and V = X^T U (p x B), `reps` times
+ * each for B right-hand sides on the problem's stream and report their average
+ * durations in microseconds (HIP events; avg_us: host, 2 entries).  Uses the
+ * grid workspace's scratch operand, so it needs a completed grid solve with at
+ * least B columns on the handle; solver state is not touched. */
+flr_status flr_profile_grid(flr_problem h, int32_t B, int32_t reps, double* avg_us);
+
 const char* flr_status_string(flr_status st);
 const char* flr_last_error(void);
 

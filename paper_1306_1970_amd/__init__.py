@@ -29,7 +29,7 @@ EXPORTS = [
     "flr_default_opts", "flr_ctx_create", "flr_ctx_destroy", "flr_create", "flr_destroy", "flr_solve",
     "flr_solve_ex", "flr_solve_grid", "flr_problem_footprint", "flr_problem_n", "flr_problem_p", "flr_problem_m",
     "flr_server_create", "flr_server_submit", "flr_server_poll", "flr_server_stats", "flr_server_destroy",
-    "flr_profile_kernels", "flr_status_string", "flr_last_error",
+    "flr_profile_kernels", "flr_profile_grid", "flr_status_string", "flr_last_error",
 ]
 
 
@@ -222,6 +222,13 @@ def flr_profile_kernels(h, reps: int):
     """Average durations (us) of the X v and X^T u kernels, HIP events on the problem's stream."""
     out = np.zeros(2)
     _check(lib().flr_profile_kernels(h, reps, out.ctypes.data))
+    return float(out[0]), float(out[1])
+
+
+def flr_profile_grid(h, B: int, reps: int):
+    """Average durations (us) of the two batched GEMMs (X O and X^T U) for B columns."""
+    out = np.zeros(2)
+    _check(lib().flr_profile_grid(h, B, reps, out.ctypes.data))
     return float(out[0]), float(out[1])
 
 

@@ -146,22 +146,53 @@ __device__ inline Aff wave_scan_rev(Aff m) {
 
 // 2x2 projective (Moebius) product used for the continued fraction
 // D_j = d_j - e_j^2 / D_{j-1} of the tridiagonal LDL^T factorization.
-struct Mob {
-  double m00, m01, m10, m11;
-};
-__device__ inline Mob mob_norm(Mob o) {
-  double mx = fmax(fmax(fabs(o.m00), fabs(o.m01)), fmax(fabs(o.m10), fabs(o.m11)));
-  if (mx > 0.0 && isfinite(mx)) {
-    int ex = ilogb(mx);
-    o.m00 = ldexp(o.m00, -ex); o.m01 = ldexp(o.m01, -ex);
-    o.m10 = ldexp(o.m10, -ex); o.m11 = ldexp(o.m11, -ex);
+// LDL^T of a symmetric tridiagonal matrix (diagonal d, sub-diagonal
+// e_j = M_{j,j-1}, e_0 = 0): L_j = e_j / D_{j-1}, D_j = d_j - e_j L_j.  The
+// pivots form one dependent chain, so a single wave runs it: the lanes stage
+// 64 (d, e) pairs at a time through this wave's LDS and prefetch the next 64
+// from memory while the chain runs on broadcast reads; lane t keeps element t
+// of the chunk for one coalesced store.  1/D_j is the hardware reciprocal
+// refined by two Newton steps (within an ulp or two of the quotient), so the
+// chain carries one multiply, one fma, the reciprocal and four fmas per
+// element.  Called by all 64 lanes of one wave; stage: 128 doubles of LDS
+// that no other wave touches meanwhile.
+__device__ inline void tri_factor_wave(const double* d, const double* e, double* L, double* invD, int64_t p,
+                                       double* stage) {
+  const int lane = threadIdx.x & 63;
+  double rprev = 0.0;  // 1/D_{-1}: e_0 = 0 makes L_0 = 0, D_0 = d_0
+  double dn = lane < p ? d[lane] : 1.0;
+  double en = lane < p ? e[lane] : 0.0;
+  for (int64_t c0 = 0; c0 < p; c0 += 64) {
+    stage[2 * lane] = dn;
+    stage[2 * lane + 1] = en;
+    const int64_t jn = c0 + 64 + lane;
+    dn = jn < p ? d[jn] : 1.0;
+    en = jn < p ? e[jn] : 0.0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    double Lout = 0.0, Iout = 0.0;
+#pragma unroll 16
+    for (int t = 0; t < 64; ++t) {
+      const double dt = stage[2 * t], et = stage[2 * t + 1];
+      const double Lt = et * rprev;
+      const double Dt = fma(-et, Lt, dt);
+      double r = __builtin_amdgcn_rcp(Dt);
+      r = fma(r, fma(-Dt, r, 1.0), r);
+      r = fma(r, fma(-Dt, r, 1.0), r);
+      rprev = r;
+      Lout = lane == t ? Lt : Lout;
+      Iout = lane == t ? r : Iout;
+    }
+    const int64_t j = c0 + lane;
+    if (j < p) {
+      L[j] = Lout;
+      invD[j] = Iout;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  return o;
-}
-// L * R (R acts first)
-__device__ inline Mob mob_mul(Mob Lm, Mob R) {
-  return mob_norm({Lm.m00 * R.m00 + Lm.m01 * R.m10, Lm.m00 * R.m01 + Lm.m01 * R.m11,
-                   Lm.m10 * R.m00 + Lm.m11 * R.m10, Lm.m10 * R.m01 + Lm.m11 * R.m11});
 }
 
 __device__ inline void copy_state(const State* sin, State* sout, const State& s) {

@@ -406,7 +406,6 @@ flr_status flr_create(flr_ctx ctx, const void* X, flr_dtype x_dtype, int64_t n, 
   CK(dalloc(h, &B.losspart, (size_t)D.rb2));
   CK(dalloc(h, &B.penpart, (size_t)D.nblk));
   CK(dalloc(h, &B.blk, (size_t)BK_N * (size_t)D.nblk));
-  CK(dalloc(h, &B.mob, 4 * (size_t)D.nblk));
   CK(dalloc(h, &B.carry, 2 * (size_t)D.nblk));
   CK(dalloc(h, &B.counter, 64));
   CK(dalloc(h, &B.st, 2));

@@ -65,6 +65,7 @@ struct GridDev {
   const double* lam2;
   ColState* st;
   const GridParams* prm;
+  const int32_t* map;  // GEMM slot -> column (active columns only, in slot order)
 };
 
 constexpr int kE = 8;              // consecutive elements per thread in a chunk
@@ -152,42 +153,12 @@ __device__ void col_tri_solve(const double* __restrict__ r, const double* __rest
 }
 
 // LDL^T factorization of one column's tridiagonal M: the continued fraction
-// D_j = d_j - e_j L_j with L_j = e_j / D_{j-1}, walked sequentially by one
-// thread (the order of the oracle's factorization; a projective-product scan
-// loses accuracy when fused edges make the weights span many decades), with
-// d and e staged through LDS in chunks.  Writes L_j and 1 / D_j.
+// D_j = d_j - e_j L_j with L_j = e_j / D_{j-1}, walked in order by the first
+// wave (a projective-product scan loses accuracy when fused edges make the
+// weights span many decades).  Writes L_j and 1 / D_j.
 __device__ void col_factor(const double* __restrict__ d, const double* __restrict__ e, double* __restrict__ L,
                            double* __restrict__ invD, int64_t p, double* sh4) {
-  const int tid = threadIdx.x;
-  constexpr int CHF = kWG;  // sh4 holds 4 x 256 doubles
-  double* cd = sh4;
-  double* ce = sh4 + CHF;
-  double* cL = sh4 + 2 * CHF;
-  double* ci = sh4 + 3 * CHF;
-  double Dp = INFINITY;
-  for (int64_t c0 = 0; c0 < p; c0 += CHF) {
-    __syncthreads();
-    const int64_t jj = c0 + tid;
-    cd[tid] = jj < p ? d[jj] : 1.0;
-    ce[tid] = jj < p ? e[jj] : 0.0;
-    __syncthreads();
-    if (tid == 0) {
-      const int nn = (int)min<int64_t>(CHF, p - c0);
-      for (int t = 0; t < nn; ++t) {
-        const double et = ce[t];
-        const double Lt = et != 0.0 ? et / Dp : 0.0;
-        const double Dt = et != 0.0 ? cd[t] - et * Lt : cd[t];
-        cL[t] = Lt;
-        ci[t] = 1.0 / Dt;
-        Dp = Dt;
-      }
-    }
-    __syncthreads();
-    if (jj < p) {
-      L[jj] = cL[tid];
-      invD[jj] = ci[tid];
-    }
-  }
+  if (threadIdx.x < 64) tri_factor_wave(d, e, L, invD, p, sh4);
   __syncthreads();
 }
 
@@ -201,8 +172,12 @@ __device__ inline double col_apply_m(const GridDev& G, int b, int64_t j, const d
   return l1 * a[j] * vj + l2 * lap;
 }
 
+// One workgroup per active column.  The GEMM operand and products (O, U, V)
+// are indexed by the column's slot in the active list; everything else by the
+// column itself.
 __global__ __launch_bounds__(kWG) void k_col(GridDev G) {
-  const int b = blockIdx.x, tid = threadIdx.x;
+  const int slot = blockIdx.x, tid = threadIdx.x;
+  const int b = G.map[slot];
   __shared__ double lds[24];
   __shared__ double sh2[2 * kWG];
   __shared__ double sh4[4 * kWG];
@@ -215,9 +190,9 @@ __global__ __launch_bounds__(kWG) void k_col(GridDev G) {
   double* r = G.r + off;
   double* pv = G.pv + off;
   double* z = G.z + off;
-  double* O = G.O + off;
-  const double* V = G.V + off;
-  const double* U = G.U + (int64_t)b * G.n;
+  double* O = G.O + (int64_t)slot * P;
+  const double* V = G.V + (int64_t)slot * P;
+  const double* U = G.U + (int64_t)slot * G.n;
 
   if (s.phase == PH_CG) {
     // q = X^T X p + M p (kept in z), p^T q
@@ -396,6 +371,15 @@ __global__ __launch_bounds__(kWG) void k_col_init(GridDev G, const double* __res
   }
 }
 
+// Compaction of the GEMM operand: new slot t takes the column that sat in old
+// slot from[t].
+__global__ __launch_bounds__(kWG) void k_gather_cols(const double* __restrict__ Oold, double* __restrict__ Onew,
+                                                     const int32_t* __restrict__ from, int64_t P) {
+  const int t = blockIdx.y;
+  const int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (j < P) Onew[(int64_t)t * P + j] = Oold[(int64_t)from[t] * P + j];
+}
+
 template <typename XT>
 __global__ __launch_bounds__(kWG) void k_widen(const XT* __restrict__ X, double* __restrict__ X64, int64_t count) {
   const int64_t stride = (int64_t)gridDim.x * kWG;
@@ -422,6 +406,9 @@ struct GridWork {
   int32_t* d_jac = nullptr;  // cap
   ColState* h_st = nullptr;  // pinned, cap
   hipEvent_t ev = nullptr;
+  double* O2 = nullptr;       // second operand buffer for compaction
+  int32_t* d_map = nullptr;   // cap
+  int32_t* d_from = nullptr;  // cap
 };
 
 namespace flr {
@@ -492,6 +479,7 @@ static flr_status grid_prepare(flr_problem h, int B) {
   GCK(al(&G.g, PB));
   GCK(al(&G.z, PB));
   GCK(al(&G.O, PB));
+  GCK(al(&gw->O2, PB));
   GCK(al(&G.V, PB));
   GCK(al(&G.U, (size_t)D.n * (size_t)B));
   GCK(al(&G.a, PB));
@@ -508,6 +496,10 @@ static flr_status grid_prepare(flr_problem h, int B) {
   gw->d_prm = reinterpret_cast<GridParams*>(tmp);
   GCK(al(&tmp, ((size_t)B * sizeof(int32_t) + 7) / 8));
   gw->d_jac = reinterpret_cast<int32_t*>(tmp);
+  GCK(al(&tmp, ((size_t)B * sizeof(int32_t) + 7) / 8));
+  gw->d_map = reinterpret_cast<int32_t*>(tmp);
+  GCK(al(&tmp, ((size_t)B * sizeof(int32_t) + 7) / 8));
+  gw->d_from = reinterpret_cast<int32_t*>(tmp);
   GCK(hipHostMalloc(reinterpret_cast<void**>(&gw->h_st), sizeof(ColState) * (size_t)B, hipHostMallocDefault));
   GCK(hipEventCreateWithFlags(&gw->ev, hipEventDisableTiming));
   if (rocblas_create_handle(&gw->blas) != rocblas_status_success) return gfail(FLR_ERR_DEVICE, "rocblas_create_handle");
@@ -525,6 +517,7 @@ static flr_status grid_prepare(flr_problem h, int B) {
   G.lam1 = gw->d_lam;
   G.lam2 = gw->d_lam + B;
   G.prm = gw->d_prm;
+  G.map = gw->d_map;
   return FLR_OK;
 }
 
@@ -580,32 +573,69 @@ static flr_status grid_run(flr_problem h, const double* l1, const double* l2, in
                      G, warm, warm ? 1 : 0, gw->d_jac);
   GCK(hipGetLastError());
   const double one = 1.0, zero = 0.0;
-  const int64_t max_steps = (int64_t)P.max_iter * ((int64_t)P.max_cg + 2) + 4;
   const int check_every = 8;
+  // every column needs at most max_iter * (max_cg + 2) + 1 steps; the host
+  // sees a finished batch up to two polling periods later
+  const int64_t max_steps = (int64_t)P.max_iter * ((int64_t)P.max_cg + 2) + 4 + 3 * check_every;
+  // active columns in slot order; compacted when enough of them have finished
+  std::vector<int32_t> act((size_t)B);
+  for (int i = 0; i < B; ++i) act[(size_t)i] = i;
+  GCK(hipMemcpyAsync(gw->d_map, act.data(), act.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  GCK(hipStreamSynchronize(h->stream));
+  G.O = gw->G.O;
+  double* Ospare = gw->O2;
   bool done = false;
   int64_t step = 0;
   bool pending = false;
   while (!done) {
     if (step >= max_steps) return gfail(FLR_ERR_DEVICE, "grid solve did not terminate within its step bound");
-    // U = X O^T : column-major U (n x B) = (X^T)^T O with X^T stored as p_pad x n (ld ldx)
-    if (rocblas_dgemm(gw->blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)D.n, B,
+    const int nact = (int)act.size();
+    // U = X O^T : column-major U (n x nact) = (X^T)^T O with X^T stored as p_pad x n (ld ldx)
+    if (rocblas_dgemm(gw->blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)D.n, nact,
                       (rocblas_int)D.p_pad, &one, h->X64, (rocblas_int)D.ldx, G.O, (rocblas_int)D.p_pad, &zero, G.U,
                       (rocblas_int)D.n) != rocblas_status_success)
       return gfail(FLR_ERR_DEVICE, "rocblas_dgemm (X O^T) failed");
-    // V = X^T U : p_pad x B
-    if (rocblas_dgemm(gw->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)D.p_pad, B,
+    // V = X^T U : p_pad x nact
+    if (rocblas_dgemm(gw->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)D.p_pad, nact,
                       (rocblas_int)D.n, &one, h->X64, (rocblas_int)D.ldx, G.U, (rocblas_int)D.n, &zero, G.V,
                       (rocblas_int)D.p_pad) != rocblas_status_success)
       return gfail(FLR_ERR_DEVICE, "rocblas_dgemm (X^T U) failed");
-    hipLaunchKernelGGL(k_col, dim3((unsigned)B), dim3(kWG), 0, h->stream, G);
+    hipLaunchKernelGGL(k_col, dim3((unsigned)nact), dim3(kWG), 0, h->stream, G);
     GCK(hipGetLastError());
     ++step;
     if (step % check_every == 0) {
       if (pending) {
         GCK(hipEventSynchronize(gw->ev));
-        bool all = true;
-        for (int b = 0; b < B && all; ++b) all = gw->h_st[b].phase == PH_DONE;
-        if (all) done = true;
+        int still = 0;
+        for (int i = 0; i < nact; ++i) still += gw->h_st[act[(size_t)i]].phase != PH_DONE;
+        if (still == 0) {
+          done = true;
+        } else if (nact - still >= std::max(8, nact / 8)) {
+          // drain, then keep only the columns still running; their operand
+          // columns move to the front of the spare buffer
+          GCK(hipStreamSynchronize(h->stream));
+          GCK(hipMemcpy(gw->h_st, G.st, sizeof(ColState) * (size_t)B, hipMemcpyDeviceToHost));
+          std::vector<int32_t> nxt, from;
+          for (int i = 0; i < nact; ++i) {
+            if (gw->h_st[act[(size_t)i]].phase != PH_DONE) {
+              nxt.push_back(act[(size_t)i]);
+              from.push_back(i);
+            }
+          }
+          if (nxt.empty()) {
+            done = true;
+          } else {
+            GCK(hipMemcpy(gw->d_from, from.data(), from.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+            GCK(hipMemcpy(gw->d_map, nxt.data(), nxt.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+            hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((D.p_pad + kWG - 1) / kWG), (unsigned)nxt.size()),
+                               dim3(kWG), 0, h->stream, G.O, Ospare, gw->d_from, D.p_pad);
+            GCK(hipGetLastError());
+            std::swap(G.O, Ospare);
+            act.swap(nxt);
+          }
+          pending = false;
+          continue;
+        }
       }
       GCK(hipMemcpyAsync(gw->h_st, G.st, sizeof(ColState) * (size_t)B, hipMemcpyDeviceToHost, h->stream));
       GCK(hipEventRecord(gw->ev, h->stream));
@@ -650,4 +680,52 @@ extern "C" flr_status flr_solve_grid(flr_problem h, const double* l1, const doub
   if (!lk.owns_lock()) return gfail(FLR_ERR_BUSY, "problem handle in use by another thread");
   if (hipSetDevice(h->ctx->device) != hipSuccess) return gfail(FLR_ERR_DEVICE, "hipSetDevice failed");
   return grid_run(h, l1, l2, B, tol, opts, beta_out, res);
+}
+
+extern "C" flr_status flr_profile_grid(flr_problem h, int32_t B, int32_t reps, double* avg_us) {
+  if (!h || !avg_us || reps < 1 || B < 1) return gfail(FLR_ERR_INVALID_ARG, "flr_profile_grid: bad arguments");
+  std::unique_lock<std::mutex> lk(h->busy, std::try_to_lock);
+  if (!lk.owns_lock()) return gfail(FLR_ERR_BUSY, "problem handle in use by another thread");
+  if (!h->grid || h->grid->cap < B || !h->X64)
+    return gfail(FLR_ERR_INVALID_ARG, "flr_profile_grid: needs a completed grid solve with at least B columns");
+  if (hipSetDevice(h->ctx->device) != hipSuccess) return gfail(FLR_ERR_DEVICE, "hipSetDevice failed");
+  GridWork* gw = h->grid;
+  const GridDev& G = gw->G;
+  const Dims& D = h->D;
+  const double one = 1.0, zero = 0.0;
+  hipEvent_t e[3];
+  for (auto& ev : e) GCK(hipEventCreate(&ev));
+  auto gemm_u = [&]() {
+    return rocblas_dgemm(gw->blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)D.n, B,
+                         (rocblas_int)D.p_pad, &one, h->X64, (rocblas_int)D.ldx, gw->O2, (rocblas_int)D.p_pad, &zero,
+                         G.U, (rocblas_int)D.n);
+  };
+  auto gemm_v = [&]() {
+    return rocblas_dgemm(gw->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)D.p_pad, B,
+                         (rocblas_int)D.n, &one, h->X64, (rocblas_int)D.ldx, G.U, (rocblas_int)D.n, &zero, G.V,
+                         (rocblas_int)D.p_pad);
+  };
+  flr_status st = FLR_OK;
+  double tot[2] = {0.0, 0.0};
+  for (int pass = 0; pass < 2 && st == FLR_OK; ++pass) {  // pass 0 warms up
+    if (hipEventRecord(e[0], h->stream) != hipSuccess) st = FLR_ERR_DEVICE;
+    for (int i = 0; i < reps && st == FLR_OK; ++i)
+      if (gemm_u() != rocblas_status_success) st = FLR_ERR_DEVICE;
+    if (st == FLR_OK && hipEventRecord(e[1], h->stream) != hipSuccess) st = FLR_ERR_DEVICE;
+    for (int i = 0; i < reps && st == FLR_OK; ++i)
+      if (gemm_v() != rocblas_status_success) st = FLR_ERR_DEVICE;
+    if (st == FLR_OK && hipEventRecord(e[2], h->stream) != hipSuccess) st = FLR_ERR_DEVICE;
+    if (st == FLR_OK && hipEventSynchronize(e[2]) != hipSuccess) st = FLR_ERR_DEVICE;
+    float m0 = 0.f, m1 = 0.f;
+    if (st == FLR_OK && (hipEventElapsedTime(&m0, e[0], e[1]) != hipSuccess ||
+                         hipEventElapsedTime(&m1, e[1], e[2]) != hipSuccess))
+      st = FLR_ERR_DEVICE;
+    tot[0] = 1e3 * m0 / reps;
+    tot[1] = 1e3 * m1 / reps;
+  }
+  for (auto& ev : e) (void)hipEventDestroy(ev);
+  if (st != FLR_OK) return gfail(st, "flr_profile_grid: a launch or event call failed");
+  avg_us[0] = tot[0];
+  avg_us[1] = tot[1];
+  return FLR_OK;
 }

@@ -87,7 +87,6 @@ struct Bufs {
   double* losspart; // rb2
   double* penpart;  // nblk
   double* blk;      // BK_N * nblk
-  double* mob;      // 4 * nblk
   double* carry;    // 2 * nblk: forward carries G, then backward carries Z
   unsigned* counter;// blocks of the current C launch that have finished
   State* st;        // 2

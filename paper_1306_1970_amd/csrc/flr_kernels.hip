@@ -391,9 +391,8 @@ __global__ __launch_bounds__(kWG) void k_gemv_b(Dims D, Bufs B, const State* __r
     if (tid == 0) B.penpart[wg] = tot;
   }
   if (!cg) {
-    // The last workgroup to finish factors M = L D L^T sequentially over all
-    // p elements (the continued fraction D_j = d_j - e_j L_j, L_j = e_j / D_{j-1}),
-    // staged through LDS in chunks; writes L and 1/D for the C launch.
+    // The last workgroup to finish factors M = L D L^T over all p elements
+    // (one wave runs the pivot chain); writes L and 1/D for the C launch.
     __shared__ int sh_flag;
     __syncthreads();
     if (tid == 0) {
@@ -405,40 +404,7 @@ __global__ __launch_bounds__(kWG) void k_gemv_b(Dims D, Bufs B, const State* __r
     }
     __syncthreads();
     if (sh_flag) {
-      double* cd = &sh_red[0][0];
-      double* ce = &sh_red[1][0];
-      double* cL = &sh_red[2][0];
-      double* ci = &sh_red[3][0];
-      constexpr int CHF = 64 * 8;
-      double Dp = INFINITY;
-      for (int64_t c0f = 0; c0f < D.p; c0f += CHF) {
-        __syncthreads();
-        for (int t = tid; t < CHF; t += kWG) {
-          const int64_t jj = c0f + t;
-          cd[t] = jj < D.p ? B.d[jj] : 1.0;
-          ce[t] = jj < D.p ? B.e[jj] : 0.0;
-        }
-        __syncthreads();
-        if (tid == 0) {
-          const int nn = (int)min<int64_t>(CHF, D.p - c0f);
-          for (int t = 0; t < nn; ++t) {
-            const double et = ce[t];
-            const double Lt = et != 0.0 ? et / Dp : 0.0;
-            const double Dt = et != 0.0 ? cd[t] - et * Lt : cd[t];
-            cL[t] = Lt;
-            ci[t] = 1.0 / Dt;
-            Dp = Dt;
-          }
-        }
-        __syncthreads();
-        for (int t = tid; t < CHF; t += kWG) {
-          const int64_t jj = c0f + t;
-          if (jj < D.p) {
-            B.L[jj] = cL[t];
-            B.invD[jj] = ci[t];
-          }
-        }
-      }
+      if (wave == 0) tri_factor_wave(B.d, B.e, B.L, B.invD, D.p, &sh_red[0][0]);
       if (tid == 0) B.counter[16] = 0u;
     }
   }

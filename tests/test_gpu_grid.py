@@ -94,3 +94,43 @@ def test_grid_columns_finish_independently(flr, ctx):
         assert res[b]["status"] == single[b].status
         assert res[b]["mm_iters"] == single[b].mm_iters
         np.testing.assert_allclose(beta[b], single[b].beta, rtol=0, atol=1e-8 * np.max(np.abs(single[b].beta)) + 1e-300)
+
+
+def test_grid_compaction_keeps_every_column(flr, ctx):
+    # 48 columns with spread-out MM counts: finished columns are dropped from the
+    # batched products several times during the solve; every column must still
+    # equal its own single solve, and the result must not depend on the batch
+    inst = flrgen.small_instance(40, 200, "chain", dtype=flrgen.F64, seed=34)
+    vals = np.logspace(-2.0, 0.8, 7)
+    l1, l2 = flrgen.grid_lambdas(vals)
+    l1, l2 = l1[:48], l2[:48]
+    prob = flr.Problem.from_instance(ctx, inst)
+    st, beta, res = prob.solve_grid(l1, l2, tol=1e-9, inner_tol=INNER)
+    st2, beta2, res2 = prob.solve_grid(l1[::-1].copy(), l2[::-1].copy(), tol=1e-9, inner_tol=INNER)
+    mms = [r["mm_iters"] for r in res]
+    print("  mm range %d..%d" % (min(mms), max(mms)), flush=True)
+    assert max(mms) > 2 * min(mms)
+    for b in range(l1.size):
+        s1 = prob.solve(l1[b], l2[b], tol=1e-9, inner_tol=INNER)
+        assert res[b]["status"] == s1.status == flr.FLR_OK
+        assert res[b]["mm_iters"] == s1.mm_iters
+        assert np.max(np.abs(beta[b] - s1.beta)) <= 1e-8 * np.max(np.abs(s1.beta))
+        # the same column in the reversed batch: identical arithmetic per column
+        rb = l1.size - 1 - b
+        assert res2[rb]["mm_iters"] == res[b]["mm_iters"]
+        assert np.array_equal(beta2[rb], beta[b])
+    prob.close()
+
+
+def test_grid_tiny_caps_report_max_iter(flr, ctx):
+    # caps far below what the solve needs: the batch stops and every column reports MAX_ITER
+    inst = flrgen.small_instance(40, 300, "lattice", dtype=flrgen.F32, seed=35)
+    l1 = np.array([0.1, 1.0])
+    l2 = np.array([0.2, 2.0])
+    prob = flr.Problem.from_instance(ctx, inst)
+    st, beta, res = prob.solve_grid(l1, l2, tol=1e-12, max_iter=1, max_cg=2)
+    prob.close()
+    assert st == flr.FLR_ERR_MAX_ITER
+    for r in res:
+        assert r["status"] == flr.FLR_ERR_MAX_ITER and r["mm_iters"] == 1 and r["cg_iters"] <= 2
+    assert np.all(np.isfinite(beta))
