@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("flr_kernels.hip", "flr_internal.h"):
+    for f in ("flr_kernels.hip", "flr_internal.h", "flr_device.h"):
         with open(os.path.join(ROOT, "paper_1306_1970_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -223,6 +223,7 @@ def grid_main(args, flr):
     B = int(l1.size)
     print("bench: workload %s n=%d p=%d m=%d B=%d" % (inst.name, inst.n, inst.p, inst.m, B), file=sys.stderr,
           flush=True)
+    os.environ.setdefault("FLR_PROGRESS", "1")
     ctx = flr.Context(0)
     prob = flr.Problem.from_instance(ctx, inst)
     # warm-up: one capped batched step prepares the FP64 copy of X, the

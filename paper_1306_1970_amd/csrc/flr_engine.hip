@@ -177,6 +177,10 @@ flr_status run_solve(flr_problem h, double l1, double l2, double tol, const flr_
   int64_t launched = 0;
   bool done = false;
   State fin{};
+  // FLR_PROGRESS=1: a line on stderr every few seconds from the polling loop
+  const char* prog_env = std::getenv("FLR_PROGRESS");
+  const bool progress = prog_env && prog_env[0] && prog_env[0] != '0';
+  auto t_prog = std::chrono::steady_clock::now();
   while (!done) {
     if (launched >= max_launches) return fail(FLR_ERR_DEVICE, "solve did not terminate within its launch bound");
     const int slot = (int)(launched & 1);
@@ -188,6 +192,11 @@ flr_status run_solve(flr_problem h, double l1, double l2, double tol, const flr_
       const int prev = (int)((launched - 2) & 1);
       HIP_OR_FAIL(hipEventSynchronize(h->ev[prev]));
       if (h->h_state[prev].phase == PH_DONE) done = true;
+      if (progress && std::chrono::steady_clock::now() - t_prog > std::chrono::seconds(5)) {
+        t_prog = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "flr solve: MM %d, PCG steps %lld, f %.12g\n", h->h_state[prev].mm_iter,
+                     (long long)h->h_state[prev].cg_total, h->h_state[prev].f_new);
+      }
     }
   }
   HIP_OR_FAIL(hipStreamSynchronize(h->stream));

@@ -18,6 +18,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -587,9 +589,17 @@ static flr_status grid_run(flr_problem h, const double* l1, const double* l2, in
   bool done = false;
   int64_t step = 0;
   bool pending = false;
+  // FLR_PROGRESS=1: a line on stderr every few seconds from the polling loop
+  const char* prog_env = std::getenv("FLR_PROGRESS");
+  const bool progress = prog_env && prog_env[0] && prog_env[0] != '0';
+  auto t_prog = std::chrono::steady_clock::now();
   while (!done) {
     if (step >= max_steps) return gfail(FLR_ERR_DEVICE, "grid solve did not terminate within its step bound");
     const int nact = (int)act.size();
+    if (progress && std::chrono::steady_clock::now() - t_prog > std::chrono::seconds(5)) {
+      t_prog = std::chrono::steady_clock::now();
+      std::fprintf(stderr, "flr grid: %lld batched steps, %d of %d columns active\n", (long long)step, nact, B);
+    }
     // U = X O^T : column-major U (n x nact) = (X^T)^T O with X^T stored as p_pad x n (ld ldx)
     if (rocblas_dgemm(gw->blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)D.n, nact,
                       (rocblas_int)D.p_pad, &one, h->X64, (rocblas_int)D.ldx, G.O, (rocblas_int)D.p_pad, &zero, G.U,
