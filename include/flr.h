@@ -62,11 +62,25 @@ typedef enum { FLR_F64 = 0, FLR_F32 = 1, FLR_BF16 = 2 } flr_dtype;
  * objective and stopping tests are always FP64). */
 typedef enum { FLR_PREC_FP64 = 0, FLR_PREC_MIXED_FP32 = 1 } flr_precision;
 
-/* Preconditioner of the PCG inner solve.  AUTO = the tridiagonal part of
- * M = lambda1 A + lambda2 B (edges (j-1, j) keep their coupling, every other
- * edge adds only to the diagonal) - exactly the paper's M for the chain - and
- * Jacobi diag(Q) when lambda1 = 0, where M is singular. */
-typedef enum { FLR_PRECOND_AUTO = 0, FLR_PRECOND_TRIDIAG = 1, FLR_PRECOND_JACOBI = 2 } flr_precond;
+/* Preconditioner of the PCG inner solve (Algorithm 2 uses M = lambda1 A +
+ * lambda2 B itself).
+ *   BAND    M exactly, through its banded Cholesky factor (bandwidth
+ *           bw = max |j - k| over E, Section 3.2): for bw >= 2, i.e. the 2-D
+ *           lattice (bw = q) and all-pairs fusion; one factorization per MM
+ *           iteration, two sequential triangular sweeps per PCG step.
+ *           Needs lambda1 > 0 and bw + 1 <= 1025.
+ *   TRIDIAG the tridiagonal part of M (edges (j-1, j) keep their coupling,
+ *           every other edge adds only to the diagonal): exactly M for the
+ *           chain; for other graphs a cheap but much weaker approximation.
+ *   JACOBI  diag(Q), for lambda1 = 0, where M is singular.
+ *   AUTO    BAND when bw >= 2 and the band fits, TRIDIAG otherwise;
+ *           JACOBI when lambda1 = 0. */
+typedef enum {
+  FLR_PRECOND_AUTO = 0,
+  FLR_PRECOND_TRIDIAG = 1,
+  FLR_PRECOND_JACOBI = 2,
+  FLR_PRECOND_BAND = 3
+} flr_precond;
 
 typedef struct {
   double eps;              /* perturbation; 0 -> 1e-8 (section 5) */

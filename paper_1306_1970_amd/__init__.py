@@ -22,7 +22,7 @@ FLR_OK, FLR_ERR_INVALID_ARG, FLR_ERR_OUT_OF_MEMORY, FLR_ERR_DEVICE = 0, 1, 2, 3
 FLR_ERR_NUMERICAL, FLR_ERR_MAX_ITER, FLR_ERR_BUSY, FLR_ERR_NOT_READY = 4, 5, 6, 7
 FLR_F64, FLR_F32, FLR_BF16 = 0, 1, 2
 FLR_PREC_FP64, FLR_PREC_MIXED_FP32 = 0, 1
-FLR_PRECOND_AUTO, FLR_PRECOND_TRIDIAG, FLR_PRECOND_JACOBI = 0, 1, 2
+FLR_PRECOND_AUTO, FLR_PRECOND_TRIDIAG, FLR_PRECOND_JACOBI, FLR_PRECOND_BAND = 0, 1, 2, 3
 
 # every symbol include/flr.h declares
 EXPORTS = [
@@ -83,6 +83,7 @@ def lib():
         L.flr_server_stats.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_size_t)]
         L.flr_server_destroy.argtypes = [vp]
         L.flr_profile_kernels.argtypes = [vp, i32, vp]
+        L.flr_profile_grid.argtypes = [vp, i32, i32, vp]
         L.flr_status_string.argtypes = [C.c_int]
         L.flr_status_string.restype = C.c_char_p
         L.flr_last_error.restype = C.c_char_p

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/flr.h"
+#include "flr_band.h"
 #include "flr_internal.h"
 #include "flr_problem.h"
 
@@ -97,14 +98,15 @@ bool is_device_ptr(const void* ptr) {
   return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
 }
 
-flr_status build_graph(flr_problem h, bool mixed) {
-  hipGraphExec_t& ge = mixed ? h->gexec_mixed : h->gexec;
-  hipGraph_t& gr = mixed ? h->graph_mixed : h->graph;
+flr_status build_graph(flr_problem h, bool mixed, bool band) {
+  hipGraphExec_t& ge = h->gexec[mixed][band];
+  hipGraph_t& gr = h->graph[mixed][band];
   if (ge) return FLR_OK;
   HIP_OR_FAIL(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
   hipError_t err = hipSuccess;
-  for (int i = 0; i < 3 * kRounds && err == hipSuccess; ++i)
-    err = launch_rotation(h->D, h->B, i & 1, i % 3, h->stream, mixed);
+  const int per = band ? 4 : 3;  // A, B, C (, K)
+  for (int i = 0; i < per * kRounds && err == hipSuccess; ++i)
+    err = launch_rotation(h->D, h->B, i & 1, i % per, h->stream, mixed);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(h->stream, &g);
   if (err != hipSuccess) return fail(FLR_ERR_DEVICE, std::string("capture launch: ") + hipGetErrorString(err));
@@ -141,10 +143,15 @@ flr_status run_solve(flr_problem h, double l1, double l2, double tol, const flr_
   P.max_iter = o->max_iter > 0 ? o->max_iter : 10000;
   P.max_cg = o->max_cg > 0 ? o->max_cg : (int32_t)std::min<int64_t>(D.p, INT32_MAX);
   int pre = o->preconditioner;
-  if (pre == FLR_PRECOND_AUTO) pre = (l1 > 0.0) ? FLR_PRECOND_TRIDIAG : FLR_PRECOND_JACOBI;
-  if (pre == FLR_PRECOND_TRIDIAG && !(l1 > 0.0))
-    return fail(FLR_ERR_INVALID_ARG, "the tridiagonal preconditioner needs lambda1 > 0 (M is singular otherwise)");
+  if (pre < FLR_PRECOND_AUTO || pre > FLR_PRECOND_BAND) return fail(FLR_ERR_INVALID_ARG, "unknown preconditioner");
+  if (pre == FLR_PRECOND_AUTO)
+    pre = !(l1 > 0.0) ? FLR_PRECOND_JACOBI : h->band_w ? FLR_PRECOND_BAND : FLR_PRECOND_TRIDIAG;
+  if ((pre == FLR_PRECOND_TRIDIAG || pre == FLR_PRECOND_BAND) && !(l1 > 0.0))
+    return fail(FLR_ERR_INVALID_ARG, "the tridiagonal and banded preconditioners need lambda1 > 0 (M is singular otherwise)");
+  if (pre == FLR_PRECOND_BAND && !h->band_w)
+    return fail(FLR_ERR_INVALID_ARG, "banded preconditioner: the edge set has bandwidth < 2 or its band is too wide");
   P.jacobi = pre == FLR_PRECOND_JACOBI ? 1 : 0;
+  P.band = pre == FLR_PRECOND_BAND ? h->band_w : 0;
   P.mixed = o->precision == FLR_PREC_MIXED_FP32 ? 1 : 0;
   HIP_OR_FAIL(hipMemcpyAsync(h->d_prm, h->h_prm, sizeof(Params), hipMemcpyHostToDevice, h->stream));
 
@@ -167,9 +174,10 @@ flr_status run_solve(flr_problem h, double l1, double l2, double tol, const flr_
   }
   HIP_OR_FAIL(launch_init(D, h->B, warm, use_warm, h->stream));
   const bool mixed = P.mixed != 0;
-  flr_status gs = build_graph(h, mixed);
+  const bool band = P.band != 0;
+  flr_status gs = build_graph(h, mixed, band);
   if (gs != FLR_OK) return gs;
-  hipGraphExec_t gexec = mixed ? h->gexec_mixed : h->gexec;
+  hipGraphExec_t gexec = h->gexec[mixed][band];
 
   // launch the captured rotation until the state machine reports done; keep
   // one launch in flight beyond the one being polled
@@ -295,10 +303,11 @@ static void problem_free(flr_problem h) {
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   flr::grid_free(h);
   if (h->X64) (void)hipFree(h->X64);
-  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
-  if (h->graph) (void)hipGraphDestroy(h->graph);
-  if (h->gexec_mixed) (void)hipGraphExecDestroy(h->gexec_mixed);
-  if (h->graph_mixed) (void)hipGraphDestroy(h->graph_mixed);
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      if (h->gexec[a][b]) (void)hipGraphExecDestroy(h->gexec[a][b]);
+      if (h->graph[a][b]) (void)hipGraphDestroy(h->graph[a][b]);
+    }
   for (void* p : h->allocs) (void)hipFree(p);
   if (h->h_prm) (void)hipHostFree(h->h_prm);
   if (h->h_state) (void)hipHostFree(h->h_state);
@@ -416,6 +425,19 @@ flr_status flr_create(flr_ctx ctx, const void* X, flr_dtype x_dtype, int64_t n, 
   CK(dalloc(h, &B.penpart, (size_t)D.nblk));
   CK(dalloc(h, &B.blk, (size_t)BK_N * (size_t)D.nblk));
   CK(dalloc(h, &B.carry, 2 * (size_t)D.nblk));
+  // banded factor of M for graphs of bandwidth >= 2 (lattice, all-pairs)
+  {
+    int64_t bw = 0;
+    for (auto& e : ev) bw = std::max(bw, e.second - e.first);
+    const int64_t W = bw + 1;
+    if (bw >= 2 && W <= kBandMaxW && (double)p * (double)W * 8.0 <= 4.0 * (1 << 30)) {
+      CK(dalloc(h, &B.Lb, (size_t)p * (size_t)W));
+      CK(dalloc(h, &B.LbT, (size_t)p * (size_t)W));
+      CK(dalloc(h, &B.invdb, (size_t)D.p_pad));
+      CK(dalloc(h, &B.btmp, (size_t)D.p_pad));
+      h->band_w = (int)W;
+    }
+  }
   CK(dalloc(h, &B.counter, 64));
   CK(dalloc(h, &B.st, 2));
   CK(dalloc(h, &h->d_prm, 1));

@@ -24,6 +24,7 @@
 #include <string>
 #include <vector>
 
+#include "flr_band.h"
 #include "flr_device.h"
 #include "flr_problem.h"
 
@@ -38,6 +39,8 @@ struct ColState {
 struct GridParams {
   double eps, tol, inner_tol, cnorm;
   int32_t max_iter, max_cg;
+  int32_t band;  // W = bandwidth + 1 when columns with lambda1 > 0 use M's banded Cholesky factor, else 0
+  int32_t pad;
 };
 
 struct GridDev {
@@ -68,6 +71,8 @@ struct GridDev {
   ColState* st;
   const GridParams* prm;
   const int32_t* map;  // GEMM slot -> column (active columns only, in slot order)
+  double* Lb;          // banded factor by columns, B x p x W (banded mode)
+  double* LbT;         // the same by rows
 };
 
 constexpr int kE = 8;              // consecutive elements per thread in a chunk
@@ -176,16 +181,23 @@ __device__ inline double col_apply_m(const GridDev& G, int b, int64_t j, const d
 
 // One workgroup per active column.  The GEMM operand and products (O, U, V)
 // are indexed by the column's slot in the active list; everything else by the
-// column itself.
+// column itself.  BAND: columns with lambda1 > 0 apply M^-1 through its banded
+// Cholesky factor (graphs of bandwidth >= 2), the others the tridiagonal part.
+template <bool BAND>
 __global__ __launch_bounds__(kWG) void k_col(GridDev G) {
   const int slot = blockIdx.x, tid = threadIdx.x;
   const int b = G.map[slot];
   __shared__ double lds[24];
   __shared__ double sh2[2 * kWG];
   __shared__ double sh4[4 * kWG];
+  __shared__ double bl[BAND ? kBandLds : 1];
   ColState s = G.st[b];
   if (s.phase == PH_DONE) return;
   const GridParams prm = *G.prm;
+  const bool use_band = BAND && !s.jacobi;
+  const int W = prm.band;
+  double* Lbb = BAND ? G.Lb + (int64_t)b * G.p * W : nullptr;
+  double* LbTb = BAND ? G.LbT + (int64_t)b * G.p * W : nullptr;
   const double l1 = G.lam1[b], l2 = G.lam2[b];
   const int64_t p = G.p, P = G.p_pad, off = (int64_t)b * P;
   double* x = G.x + off;
@@ -220,7 +232,10 @@ __global__ __launch_bounds__(kWG) void k_col(GridDev G) {
       r[j] = fma(-nu, z[j], r[j]);
     }
     __syncthreads();
-    col_tri_solve(r, G.L + off, G.invD + off, G.g + off, z, p, lds, sh2);
+    if (use_band)
+      band_solve(r, G.g + off, z, Lbb, LbTb, G.invD + off, p, W, bl);
+    else
+      col_tri_solve(r, G.L + off, G.invD + off, G.g + off, z, p, lds, sh2);
     double rzp = 0.0, rrp = 0.0;
     for (int64_t j = tid; j < p; j += kWG) {
       rzp = fma(r[j], z[j], rzp);
@@ -318,11 +333,25 @@ __global__ __launch_bounds__(kWG) void k_col(GridDev G) {
     e[j] = ej;
   }
   __syncthreads();
-  col_factor(d, e, G.L + off, G.invD + off, p, sh4);
+  if (use_band) {
+    band_assemble(d, G.rowptr, G.col, w, l2, p, W, Lbb);
+    if (!band_factor(Lbb, LbTb, G.invD + off, p, W, bl)) {
+      s.status = ST_NUMERICAL;
+      s.phase = PH_DONE;
+      for (int64_t j = tid; j < P; j += kWG) O[j] = 0.0;
+      if (tid == 0) G.st[b] = s;
+      return;
+    }
+  } else {
+    col_factor(d, e, G.L + off, G.invD + off, p, sh4);
+  }
   // r0 = c - (X^T X + M) x
   for (int64_t j = tid; j < p; j += kWG) r[j] = G.c[j] - (V[j] + col_apply_m(G, b, j, x, l1, l2));
   __syncthreads();
-  col_tri_solve(r, G.L + off, G.invD + off, G.g + off, z, p, lds, sh2);
+  if (use_band)
+    band_solve(r, G.g + off, z, Lbb, LbTb, G.invD + off, p, W, bl);
+  else
+    col_tri_solve(r, G.L + off, G.invD + off, G.g + off, z, p, lds, sh2);
   double rzp = 0.0, rrp = 0.0;
   for (int64_t j = tid; j < p; j += kWG) {
     rzp = fma(r[j], z[j], rzp);
@@ -440,7 +469,7 @@ static flr_status gfail(flr_status st, const std::string& m) {
                    std::string(#expr) + ": " + hipGetErrorString(e_));                                      \
   } while (0)
 
-static flr_status grid_prepare(flr_problem h, int B) {
+static flr_status grid_prepare(flr_problem h, int B, bool band) {
   const Dims& D = h->D;
   if (!h->X64) {
     GCK(hipMalloc(reinterpret_cast<void**>(&h->X64), (size_t)D.n * (size_t)D.ldx * sizeof(double)));
@@ -460,7 +489,18 @@ static flr_status grid_prepare(flr_problem h, int B) {
     }
     GCK(hipGetLastError());
   }
-  if (h->grid && h->grid->cap >= B) return FLR_OK;
+  if (h->grid && h->grid->cap >= B) {
+    if (band && !h->grid->G.Lb) {
+      GridWork* gw = h->grid;
+      const size_t nb = (size_t)gw->cap * (size_t)D.p * (size_t)h->band_w;
+      for (double** ptr : {&gw->G.Lb, &gw->G.LbT}) {
+        GCK(hipMalloc(reinterpret_cast<void**>(ptr), nb * sizeof(double)));
+        gw->allocs.push_back(*ptr);
+        GCK(hipMemsetAsync(*ptr, 0, nb * sizeof(double), h->stream));
+      }
+    }
+    return FLR_OK;
+  }
   grid_free(h);
   GridWork* gw = new GridWork;
   h->grid = gw;
@@ -490,6 +530,10 @@ static flr_status grid_prepare(flr_problem h, int B) {
   GCK(al(&G.L, PB));
   GCK(al(&G.invD, PB));
   GCK(al(&G.w, (size_t)std::max<int64_t>(h->nnz, 1) * (size_t)B));
+  if (band) {
+    GCK(al(&G.Lb, (size_t)B * (size_t)D.p * (size_t)h->band_w));
+    GCK(al(&G.LbT, (size_t)B * (size_t)D.p * (size_t)h->band_w));
+  }
   GCK(al(&gw->d_lam, 2 * (size_t)B));
   double* tmp = nullptr;
   GCK(al(&tmp, (sizeof(ColState) * (size_t)B + 7) / 8));
@@ -530,7 +574,8 @@ static flr_status grid_run(flr_problem h, const double* l1, const double* l2, in
   flr_default_opts(&dflt);
   if (!o) o = &dflt;
   if (o->precision != FLR_PREC_FP64) return gfail(FLR_ERR_INVALID_ARG, "grid solves run in FP64 in this build");
-  flr_status ps = grid_prepare(h, B);
+  const bool want_band = h->band_w && (o->preconditioner == FLR_PRECOND_AUTO || o->preconditioner == FLR_PRECOND_BAND);
+  flr_status ps = grid_prepare(h, B, want_band);
   if (ps != FLR_OK) return ps;
   GridWork* gw = h->grid;
   GridDev G = gw->G;
@@ -545,15 +590,21 @@ static flr_status grid_run(flr_problem h, const double* l1, const double* l2, in
   P.max_cg = o->max_cg > 0 ? o->max_cg : (int32_t)std::min<int64_t>(D.p, INT32_MAX);
   std::vector<double> lam((size_t)2 * B);
   std::vector<int32_t> jac((size_t)B);
+  const int pre0 = o->preconditioner;
+  if (pre0 < FLR_PRECOND_AUTO || pre0 > FLR_PRECOND_BAND) return gfail(FLR_ERR_INVALID_ARG, "unknown preconditioner");
+  if (pre0 == FLR_PRECOND_BAND && !h->band_w)
+    return gfail(FLR_ERR_INVALID_ARG, "banded preconditioner: the edge set has bandwidth < 2 or its band is too wide");
+  const bool band = h->band_w && (pre0 == FLR_PRECOND_AUTO || pre0 == FLR_PRECOND_BAND);
   for (int i = 0; i < B; ++i) {
     lam[(size_t)i] = l1[i];
     lam[(size_t)B + i] = l2[i];
-    int pre = o->preconditioner;
+    int pre = pre0;
     if (pre == FLR_PRECOND_AUTO) pre = l1[i] > 0.0 ? FLR_PRECOND_TRIDIAG : FLR_PRECOND_JACOBI;
-    if (pre == FLR_PRECOND_TRIDIAG && !(l1[i] > 0.0))
-      return gfail(FLR_ERR_INVALID_ARG, "the tridiagonal preconditioner needs lambda1 > 0");
+    if ((pre == FLR_PRECOND_TRIDIAG || pre == FLR_PRECOND_BAND) && !(l1[i] > 0.0))
+      return gfail(FLR_ERR_INVALID_ARG, "the tridiagonal and banded preconditioners need lambda1 > 0");
     jac[(size_t)i] = pre == FLR_PRECOND_JACOBI ? 1 : 0;
   }
+  P.band = band ? h->band_w : 0;
   G.lam1 = gw->d_lam;
   G.lam2 = gw->d_lam + B;
   GCK(hipMemcpyAsync(gw->d_lam, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
@@ -610,7 +661,10 @@ static flr_status grid_run(flr_problem h, const double* l1, const double* l2, in
                       (rocblas_int)D.n, &one, h->X64, (rocblas_int)D.ldx, G.U, (rocblas_int)D.n, &zero, G.V,
                       (rocblas_int)D.p_pad) != rocblas_status_success)
       return gfail(FLR_ERR_DEVICE, "rocblas_dgemm (X^T U) failed");
-    hipLaunchKernelGGL(k_col, dim3((unsigned)nact), dim3(kWG), 0, h->stream, G);
+    if (P.band)
+      hipLaunchKernelGGL(k_col<true>, dim3((unsigned)nact), dim3(kWG), 0, h->stream, G);
+    else
+      hipLaunchKernelGGL(k_col<false>, dim3((unsigned)nact), dim3(kWG), 0, h->stream, G);
     GCK(hipGetLastError());
     ++step;
     if (step % check_every == 0) {

@@ -1,7 +1,9 @@
 // Internal layout shared by the HIP kernels and the host engine.
 //
 // One solve is a device-resident state machine.  Every launch is one of three
-// kernels that run in a fixed rotation A, B, C (a hipGraph holds S rounds):
+// kernels that run in a fixed rotation A, B, C (a hipGraph holds S rounds);
+// when M is banded with bandwidth >= 2 a fourth, K, applies M^-1 through its
+// banded Cholesky factor after C:
 //   A  row-panel GEMV   u = X v            (v = new CG direction, or the MM iterate)
 //   B  column-panel GEMV q = X^T u (+ M v)  (plus, at an MM boundary: objective
 //                                            partials, reweighting, factorization products)
@@ -23,7 +25,9 @@ constexpr int kMaxC1 = 2048;      // max columns of an A tile
 constexpr int kMaxR2 = 1024;      // max rows of a B tile
 constexpr int kMaxBlocks = 1024;  // max solver blocks -> p_pad <= 262144
 
-enum Phase : int32_t { PH_CG = 0, PH_END = 1, PH_DONE = 2 };
+// PH_BANDMM: an MM step goes on and M is banded (bandwidth >= 2): the fourth
+// launch of the rotation factors M and solves with the new residual.
+enum Phase : int32_t { PH_CG = 0, PH_END = 1, PH_DONE = 2, PH_BANDMM = 3 };
 enum SolveStatus : int32_t { ST_OK = 0, ST_MAX_ITER = 1, ST_NUMERICAL = 2 };
 
 // Block scalars of the partitioned tridiagonal solve (index into blk[]).
@@ -43,6 +47,8 @@ enum BlkField : int {
 struct Params {
   double lam1, lam2, eps, tol, inner_tol, cnorm;
   int32_t max_iter, max_cg, jacobi, mixed;
+  int32_t band;  // W = bandwidth + 1 when M is applied through its banded Cholesky factor, else 0
+  int32_t pad;
 };
 
 struct State {
@@ -88,6 +94,10 @@ struct Bufs {
   double* penpart;  // nblk
   double* blk;      // BK_N * nblk
   double* carry;    // 2 * nblk: forward carries G, then backward carries Z
+  double* Lb;       // banded Cholesky factor of M by columns, p x W (banded mode only)
+  double* LbT;      // the same by rows
+  double* invdb;    // 1 / L_jj
+  double* btmp;     // intermediate of the two triangular sweeps
   unsigned* counter;// blocks of the current C launch that have finished
   State* st;        // 2
   const Params* prm;

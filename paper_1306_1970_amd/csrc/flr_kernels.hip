@@ -13,6 +13,7 @@
 #include <cmath>
 
 #include "flr_device.h"
+#include "flr_band.h"
 #include "flr_internal.h"
 
 namespace flr {
@@ -76,7 +77,11 @@ __global__ __launch_bounds__(kWG) void k_init(Dims D, Bufs B, const double* __re
     B.yv[j] = 0.0;
     B.pbuf[j] = 0.0;
     B.pbuf[D.p_pad + j] = 0.0;
+    // the banded mode rebuilds z from yv alone (gains and carries stay zero)
+    B.sig[j] = 0.0;
+    B.psi[j] = 0.0;
   }
+  if (j < 2 * (int64_t)D.nblk) B.carry[j] = 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     State s;
     s.phase = PH_END;
@@ -404,7 +409,7 @@ __global__ __launch_bounds__(kWG) void k_gemv_b(Dims D, Bufs B, const State* __r
     }
     __syncthreads();
     if (sh_flag) {
-      if (wave == 0) tri_factor_wave(B.d, B.e, B.L, B.invD, D.p, &sh_red[0][0]);
+      if (wave == 0 && !prm.band) tri_factor_wave(B.d, B.e, B.L, B.invD, D.p, &sh_red[0][0]);
       if (tid == 0) B.counter[16] = 0u;
     }
   }
@@ -696,6 +701,16 @@ __global__ __launch_bounds__(kWG) void k_block(Dims D, Bufs B, const State* __re
       rj = fma(-nu, q, rj0);
       B.r[j] = rj;
     }
+    if (prm.band) {  // the K launch solves with the new residual
+      if (b == 0 && tid == 0) {
+        State o = s;
+        o.cg_iter = s.cg_iter + 1;
+        o.cg_total = s.cg_total + 1;
+        o.nu = nu;
+        *sout = o;
+      }
+      return;
+    }
     sh_L[tid] = Lj;
     if (tid == 0) sh_L[kBlk] = Lnb;
     __syncthreads();
@@ -761,6 +776,14 @@ __global__ __launch_bounds__(kWG) void k_block(Dims D, Bufs B, const State* __re
   o.f_old = f_new;
   o.first_cg = 1;
   o.cg_iter = 0;
+  if (prm.band) {  // r0 = c - (X^T X + M) x0; the K launch factors M and solves
+    if (real) B.r[j] = cj - (qsum + apply_m(B, prm, j, B.x));
+    if (b == 0 && tid == 0) {
+      o.phase = PH_BANDMM;
+      *sout = o;
+    }
+    return;
+  }
   sh_L[tid] = Lj;
   if (tid == 0) sh_L[kBlk] = Lnb;
   __syncthreads();
@@ -805,6 +828,58 @@ __global__ __launch_bounds__(kWG) void k_block(Dims D, Bufs B, const State* __re
 }
 
 // ---------------------------------------------------------------------------
+// K (banded M, one workgroup): z = M^-1 r through the banded Cholesky factor,
+// r^T z, ||r||, the inner stopping test of Algorithm 2 and gamma.  After an
+// MM boundary (PH_BANDMM) it first assembles M from the new weights and
+// factors it.  A then rebuilds p from z = yv (gains and carries are zero).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kWG) void k_band(Dims D, Bufs B, const State* __restrict__ sin,
+                                              State* __restrict__ sout, const Params* __restrict__ prmp) {
+  __shared__ double lds[kBandLds];
+  __shared__ double red[24];
+  const State s = *sin;
+  const int tid = threadIdx.x;
+  if (s.phase == PH_DONE || s.phase == PH_END) {  // nothing to solve (finished, or not banded mode)
+    if (tid == 0) *sout = s;
+    return;
+  }
+  const Params prm = *prmp;
+  const int W = prm.band;
+  const bool mm = s.phase == PH_BANDMM;
+  State o = s;
+  if (mm) {
+    band_assemble(B.d, B.rowptr, B.col, B.w, prm.lam2, D.p, W, B.Lb);
+    if (!band_factor(B.Lb, B.LbT, B.invdb, D.p, W, lds)) {
+      if (tid == 0) {
+        o.phase = PH_DONE;
+        o.status = ST_NUMERICAL;
+        *sout = o;
+      }
+      return;
+    }
+    __syncthreads();
+  }
+  band_solve(B.r, B.btmp, B.yv, B.Lb, B.LbT, B.invdb, D.p, W, lds);
+  double rzp = 0.0, rrp = 0.0;
+  for (int64_t j = tid; j < D.p; j += kWG) {
+    const double rj = B.r[j];
+    rzp = fma(rj, B.yv[j], rzp);
+    rrp = fma(rj, rj, rrp);
+  }
+  double sums[4] = {rzp, rrp, 0.0, 0.0};
+  wg_sum4(sums, red);
+  if (tid == 0) {
+    const double rz = sums[0], rn = sqrt(sums[1]) / prm.cnorm;
+    const bool done = !(rn > prm.inner_tol) || (mm ? prm.max_cg <= 0 : o.cg_iter >= prm.max_cg);
+    o.rel_res = rn;
+    o.gamma = mm ? 0.0 : rz / s.rz;
+    o.rz = rz;
+    o.phase = done ? PH_END : PH_CG;
+    *sout = o;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
 template <typename XT, bool MX>
@@ -817,6 +892,9 @@ static hipError_t launch_rotation_t(const Dims& D, const Bufs& B, int par, int w
       break;
     case 1:
       hipLaunchKernelGGL((k_gemv_b<XT, MX>), dim3(D.gridB), dim3(kWG), 0, st, D, B, sin, sout, B.prm);
+      break;
+    case 3:
+      hipLaunchKernelGGL(k_band, dim3(1), dim3(kWG), 0, st, D, B, sin, sout, B.prm);
       break;
     default:
       hipLaunchKernelGGL(k_block, dim3(D.nblk), dim3(kWG), 0, st, D, B, sin, sout, B.prm);

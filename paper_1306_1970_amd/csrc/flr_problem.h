@@ -22,8 +22,8 @@ struct flr_ctx_s {
   bool own_stream = false;
 };
 
-// Number of A/B/C rounds captured in one graph (3*S launches; S even keeps
-// the state parity fixed per node).
+// Number of rotation rounds captured in one graph (3*S launches, or 4*S with
+// the banded solve; S even keeps the state parity fixed per node).
 static constexpr int kRounds = 16;
 
 struct flr_problem_s {
@@ -38,10 +38,9 @@ struct flr_problem_s {
   Params* h_prm = nullptr;  // pinned
   State* h_state = nullptr; // pinned, 2 slots
   hipEvent_t ev[2] = {nullptr, nullptr};
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  hipGraph_t graph_mixed = nullptr;
-  hipGraphExec_t gexec_mixed = nullptr;
+  hipGraph_t graph[2][2] = {};         // [mixed][banded]
+  hipGraphExec_t gexec[2][2] = {};
+  int band_w = 0;                       // bandwidth + 1 of E when the banded factor is allocated, else 0
   std::vector<void*> allocs;
   size_t footprint = 0;
   bool has_solution = false;

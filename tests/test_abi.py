@@ -46,3 +46,12 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(flr.flr_result) == 48
     o = flr.default_opts()
     assert o.eps == 1e-8 and o.max_iter == 0 and o.precision == flr.FLR_PREC_FP64
+
+
+def test_every_export_declares_argtypes():
+    # a function called without argtypes gets its pointer arguments truncated to C int
+    lib = flr.lib()
+    for name in flr.EXPORTS:
+        if name in ("flr_last_error",):
+            continue
+        assert getattr(lib, name).argtypes is not None, name

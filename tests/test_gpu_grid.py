@@ -134,3 +134,22 @@ def test_grid_tiny_caps_report_max_iter(flr, ctx):
     for r in res:
         assert r["status"] == flr.FLR_ERR_MAX_ITER and r["mm_iters"] == 1 and r["cg_iters"] <= 2
     assert np.all(np.isfinite(beta))
+
+
+def test_grid_lattice_banded(flr, ctx):
+    # lattice columns apply M^-1 through the banded factor (one per column), default inner cap
+    inst = flrgen.small_instance(80, 144, "lattice", dtype=flrgen.F32, seed=36)
+    l1, l2 = flrgen.grid_lambdas(np.array([0.1, 0.6]))
+    prob = flr.Problem.from_instance(ctx, inst)
+    st, beta, res = prob.solve_grid(l1, l2, tol=1e-7, inner_tol=INNER)
+    prob.close()
+    P = oracle.Problem.from_instance(inst)
+    for b in range(l1.size):
+        ref = oracle.solve(P, l1[b], l2[b], tol=1e-7, inner_tol=INNER, method=oracle.ALG2)
+        err = np.max(np.abs(beta[b] - ref.beta)) / np.max(np.abs(ref.beta))
+        print("  col %d grid mm=%d cg=%d | oracle mm=%d cg=%d err=%.2e" % (
+            b, res[b]["mm_iters"], res[b]["cg_iters"], ref.mm_iters, ref.cg_iters, err), flush=True)
+        assert res[b]["status"] == flr.FLR_OK
+        assert res[b]["mm_iters"] == ref.mm_iters
+        assert err <= 1e-8
+        assert abs(res[b]["cg_iters"] - ref.cg_iters) <= max(5, ref.cg_iters // 50)
