@@ -6,17 +6,20 @@
 // the factor is computed once per MM iteration and every PCG step applies it
 // with two triangular sweeps.
 //
-// Layouts (W = bw + 1 entries per row / column):
-//   Lb  column-major band, Lb[j*W + k] = L_{j+k, j}   (column j of L)
-//   LbT row-major band,    LbT[i*W + k] = L_{i, i-k}  (row i of L)
-//   invd[j] = 1 / L_jj
+// Layouts (W = bw + 1 entries per row / column), stored as the sweeps use
+// them, i.e. divided by the diagonal of the step that applies them:
+//   Lb  column-major band, Lb[j*W + k]  = L_{j+k, j} / L_jj  (column j; k >= 1)
+//   LbT row-major band,    LbT[i*W + k] = L_{i, i-k} / L_ii  (row i; k >= 1)
+//   Lb[j*W] = LbT[j*W] = L_jj, invd[j] = 1 / L_jj
 // Both sweeps walk one dependent chain of length p, so one wave runs each:
 // the not-yet-final right-hand sides of the next bw elements sit in a ring of
 // 64*NR registers across the wave's lanes (element t in slot t mod 64*NR),
-// each step reads the current element from its lane, scales it by 1/L_jj and
-// subtracts its multiple from the ring with one fma per register; the other
-// three waves of the workgroup stage the multipliers of the coming steps into
-// LDS, already permuted to the ring's slot order.
+// each step reads the current element's right-hand side b_j from its lane and
+// subtracts b_j times (multiplier / L_jj) from the ring with one fma per
+// register; the solution b_j / L_jj of a chunk of 64 elements is formed once
+// the chunk is done.  The other three waves of the workgroup stage the scaled
+// multipliers of the coming steps into LDS, permuted to the ring's slot order,
+// with their loads issued a sub-chunk ahead.
 #pragma once
 #include "flr_device.h"
 
@@ -58,51 +61,67 @@ __device__ inline void band_assemble(const double* __restrict__ d, const int32_t
 // Right-looking Cholesky of the assembled band, in place.  Step j takes the
 // pivot, writes column j of L (to Lb and, transposed, to LbT) and subtracts
 // the outer product of its scaled column from columns j+1 .. j+bw.  Those
-// columns live in an LDS ring of W + 1 slots when it fits (column j + W is
-// loaded into the slot column j - 1 left), else they are updated in Lb and
-// column j is scaled one step later.  256 threads; returns false in every
-// thread when a pivot is not positive and finite.
+// columns live in an LDS ring of W + 4 slots when it fits: column j + W + 3
+// enters at step j (into the slot column j - 1 left) from registers loaded
+// four steps earlier, so the global loads overlap four steps of updates.
+// Otherwise the columns are updated in Lb and column j is scaled one step
+// later.  256 threads; returns false in every thread when a pivot is not
+// positive and finite.
 __device__ inline bool band_factor(double* __restrict__ Lb, double* __restrict__ LbT, double* __restrict__ invd,
                                    int64_t p, int W, double* __restrict__ lds) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int tx = tid & 15, ty = tid >> 4;
-  const int R = W + 1;
-  const bool ring = (int64_t)R * W <= kBandLds;
-  if (ring) {
-    const int64_t ncol = p < W ? p : W;
-    for (int64_t i = tid; i < ncol * W; i += nt) lds[i] = Lb[i];
-  }
-  __syncthreads();
+  constexpr int E = 4;  // extra ring slots = load-ahead distance in steps
+  const int R = W + E;
+  const bool ring = (int64_t)R * W <= kBandLds && W <= nt;
   bool ok = true;
-  double inv_prev = 0.0, ljj_prev = 0.0;
-  int dmax_prev = -1;
-  for (int64_t j = 0; j < p; ++j) {
-    const int dmax = (int)((p - 1 - j) < (int64_t)(W - 1) ? (p - 1 - j) : (int64_t)(W - 1));
-    if (ring) {
-      const double* cj = lds + (j % R) * W;
-      const double piv = cj[0];
-      if (!(piv > 0.0) || !isfinite(piv)) {
-        ok = false;
-        break;
+  if (ring) {
+    const int64_t ncol = p < (int64_t)(W + E - 1) ? p : (int64_t)(W + E - 1);
+    for (int64_t i = tid; i < ncol * W; i += nt) lds[i] = Lb[i];
+    double nxt[E];  // entry tid of columns j + W + 3 (+ u) waiting to enter the ring
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+      const int64_t c = (int64_t)W + E - 1 + u;
+      nxt[u] = (tid < W && c < p) ? Lb[c * W + tid] : 0.0;
+    }
+    __syncthreads();
+    for (int64_t jb = 0; jb < p && ok; jb += E) {
+#pragma unroll
+      for (int u = 0; u < E; ++u) {
+        const int64_t j = jb + u;
+        if (j >= p) break;
+        const int dmax = (int)((p - 1 - j) < (int64_t)(W - 1) ? (p - 1 - j) : (int64_t)(W - 1));
+        const double* cj = lds + (j % R) * W;
+        const double piv = cj[0];
+        if (!(piv > 0.0) || !isfinite(piv)) {
+          ok = false;
+          break;
+        }
+        const double ljj = sqrt(piv), inv = 1.0 / ljj;
+        for (int d = tid; d <= dmax; d += nt) {
+          const double v = d ? cj[d] * inv : ljj;
+          Lb[j * W + d] = d ? v * inv : ljj;
+          LbT[(j + d) * W + d] = v;
+        }
+        if (tid == 0) invd[j] = inv;
+        for (int d1 = 1 + ty; d1 <= dmax; d1 += 16) {
+          const double s1 = cj[d1] * inv;
+          double* tgt = lds + ((j + d1) % R) * W - d1;
+          for (int d2 = d1 + tx; d2 <= dmax; d2 += 16) tgt[d2] = fma(-s1, cj[d2] * inv, tgt[d2]);
+        }
+        const int64_t cin = j + W + E - 1;  // enters the ring now; first updated at step j + E
+        if (tid < W && cin < p) lds[(cin % R) * W + tid] = nxt[u];
+        const int64_t cnx = cin + E;
+        nxt[u] = (tid < W && cnx < p) ? Lb[cnx * W + tid] : 0.0;
+        lds_barrier();  // the loads of nxt stay in flight for E steps
       }
-      const double ljj = sqrt(piv), inv = 1.0 / ljj;
-      for (int d = tid; d <= dmax; d += nt) {
-        const double v = d ? cj[d] * inv : ljj;
-        Lb[j * W + d] = v;
-        LbT[(j + d) * W + d] = v;
-      }
-      if (tid == 0) invd[j] = inv;
-      for (int d1 = 1 + ty; d1 <= dmax; d1 += 16) {
-        const double s1 = cj[d1] * inv;
-        double* tgt = lds + ((j + d1) % R) * W - d1;
-        for (int d2 = d1 + tx; d2 <= dmax; d2 += 16) tgt[d2] = fma(-s1, cj[d2] * inv, tgt[d2]);
-      }
-      if (j + W < p) {
-        double* slot = lds + ((j + W) % R) * W;
-        for (int d = tid; d < W; d += nt) slot[d] = Lb[(j + W) * W + d];
-      }
-      __syncthreads();
-    } else {
+    }
+  } else {
+    __syncthreads();
+    double inv_prev = 0.0, ljj_prev = 0.0;
+    int dmax_prev = -1;
+    for (int64_t j = 0; j < p; ++j) {
+      const int dmax = (int)((p - 1 - j) < (int64_t)(W - 1) ? (p - 1 - j) : (int64_t)(W - 1));
       double* cj = Lb + j * W;
       const double piv = cj[0];
       if (!(piv > 0.0) || !isfinite(piv)) {
@@ -117,9 +136,9 @@ __device__ inline bool band_factor(double* __restrict__ Lb, double* __restrict__
         LbT[(j + d) * W + d] = v;
       }
       if (tid == 0) invd[j] = inv;
-      if (j > 0)  // column j - 1 is final: scale it in place
+      if (j > 0)  // column j - 1 is final: scale it in place (by 1/L_jj twice, see above)
         for (int d = tid; d <= dmax_prev; d += nt)
-          Lb[(j - 1) * W + d] = d ? Lb[(j - 1) * W + d] * inv_prev : ljj_prev;
+          Lb[(j - 1) * W + d] = d ? Lb[(j - 1) * W + d] * (inv_prev * inv_prev) : ljj_prev;
       __syncthreads();
       for (int d1 = 1 + ty; d1 <= dmax; d1 += 16) {
         const double s1 = colj[d1];
@@ -131,9 +150,18 @@ __device__ inline bool band_factor(double* __restrict__ Lb, double* __restrict__
       dmax_prev = dmax;
       __syncthreads();
     }
+    if (ok && p > 0) {
+      for (int d = tid; d <= dmax_prev; d += nt)
+        Lb[(p - 1) * W + d] = d ? Lb[(p - 1) * W + d] * (inv_prev * inv_prev) : ljj_prev;
+      __syncthreads();
+    }
   }
-  if (ok && !ring && p > 0) {
-    for (int d = tid; d <= dmax_prev; d += nt) Lb[(p - 1) * W + d] = d ? Lb[(p - 1) * W + d] * inv_prev : ljj_prev;
+  if (ok) {  // rows of L scaled by their own 1/L_ii (the backward sweep's multipliers)
+    const int64_t tot = p * (int64_t)W;
+    for (int64_t idx = tid; idx < tot; idx += nt) {
+      const int64_t i = idx / W;
+      if (idx - i * W) LbT[idx] *= invd[i];
+    }
     __syncthreads();
   }
   return ok;
@@ -145,29 +173,54 @@ __device__ inline double readlane_f64(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-// SC steps of the sweep by wave 0, ring register R0 holding the current chunk.
-template <int NR, int SC, int R0>
-__device__ __forceinline__ void band_steps(double (&reg)[NR], double& yout, double idv, const double* __restrict__ buf,
-                                  int64_t t0, int lc0, int64_t p, int lane) {
+// SC steps of the sweep by wave 0: sub-chunk SUB of the chunk held in ring
+// register R0 (elements t0 .. t0 + SC - 1, lanes SUB*SC ...).  The staged
+// multipliers already include 1/L_jj.  The dependent chain is one fma per
+// step, on values every lane holds: bu = b_j (final), and the next element's
+// final value b_{j+1} = pre - m b_j, where pre is b_{j+1} after the steps
+// before j (read from its lane one step early) and m its multiplier at step
+// j (a broadcast LDS read).  The ring update - one fma per register - and
+// those reads stay off that chain.
+template <int NR, int SC, int R0, int SUB>
+__device__ __forceinline__ void band_steps(double (&reg)[NR], double& bu, double& pre, const double* __restrict__ buf,
+                                           int lane) {
+  constexpr int LC0 = SUB * SC;
+  double mc[NR], mn[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) mc[r] = buf[r * 64 + lane];
 #pragma unroll
   for (int l = 0; l < SC; ++l) {
-    if (t0 + l >= p) break;
-    const int lc = lc0 + l;
-    const double yj = readlane_f64(reg[R0], lc) * readlane_f64(idv, lc);
-    yout = lane == lc ? yj : yout;
+    // ring position of elements j + 1 and j + 2 (compile time)
+    const int s1 = R0 * 64 + LC0 + l + 1, s2 = s1 + 1;
+    const int r1 = (s1 / 64) % NR, ln1 = s1 % 64;
+    const int r2 = (s2 / 64) % NR, ln2 = s2 % 64;
+    if (l + 1 < SC) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r) reg[r] = fma(-buf[(l * NR + r) * 64 + lane], yj, reg[r]);
+      for (int r = 0; r < NR; ++r) mn[r] = buf[((l + 1) * NR + r) * 64 + lane];
+    }
+    const double m1 = buf[(l * NR + r1) * 64 + ln1];  // broadcast
+#pragma unroll
+    for (int r = 0; r < NR; ++r) reg[r] = fma(-mc[r], bu, reg[r]);
+    const double pre2 = readlane_f64(reg[r2], ln2);
+    bu = fma(-m1, bu, pre);
+    pre = pre2;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) mc[r] = mn[r];
   }
 }
 
-template <int NR, int SC, int R0>
-__device__ __forceinline__ void band_steps_sw(int r0, double (&reg)[NR], double& yout, double idv, const double* buf,
-                                     int64_t t0, int lc0, int64_t p, int lane) {
+template <int NR, int SC, int R0, int SUB>
+__device__ __forceinline__ void band_steps_sw(int r0, int sub, double (&reg)[NR], double& bu, double& pre,
+                                              const double* buf, int lane) {
   if constexpr (R0 < NR) {
-    if (r0 == R0)
-      band_steps<NR, SC, R0>(reg, yout, idv, buf, t0, lc0, p, lane);
-    else
-      band_steps_sw<NR, SC, R0 + 1>(r0, reg, yout, idv, buf, t0, lc0, p, lane);
+    if constexpr (SUB < 64 / SC) {
+      if (r0 == R0 && sub == SUB)
+        band_steps<NR, SC, R0, SUB>(reg, bu, pre, buf, lane);
+      else
+        band_steps_sw<NR, SC, R0, SUB + 1>(r0, sub, reg, bu, pre, buf, lane);
+    } else {
+      band_steps_sw<NR, SC, R0 + 1, 0>(r0, sub, reg, bu, pre, buf, lane);
+    }
   }
 }
 
@@ -187,35 +240,48 @@ __device__ __forceinline__ void band_sweep_t(const double* __restrict__ b, doubl
   const int bw = W - 1;
   const int64_t nsub = (p + SC - 1) / SC;
   auto elem = [&](int64_t t) { return fwd ? t : p - 1 - t; };
-  // Waves 1..3 stage sub-chunk s: all PER loads of a thread are issued before
-  // any is written to LDS, and they are issued one sub-chunk early (into
-  // pend), so their latency hides behind wave 0's steps.
+  // Waves 1..3 stage sub-chunk s.  Each of their threads owns fixed ring
+  // slots (register r, lane ln) and walks the SC steps: the distance k from
+  // the step's element to the slot's element drops by one per step, so the
+  // multiplier's address advances by W - 1.  All loads of a thread are
+  // issued before any is written to LDS, one sub-chunk early (into pend), so
+  // their latency hides behind wave 0's steps.
   constexpr int NL = kWG - 64;
-  constexpr int PER = (BUF + NL - 1) / NL;
+  constexpr int SPT = (NR * 64 + NL - 1) / NL;  // ring slots per staging thread
+  constexpr int PER = SC * SPT;
   double pend[PER];
   auto stage_load = [&](int64_t s) {
     const int64_t t0 = s * SC;
     const int r0 = (int)((t0 / 64) % NR);
     const int lc0 = (int)(t0 % 64);
 #pragma unroll
-    for (int m = 0; m < PER; ++m) {
-      const int i = tid - 64 + NL * m;
-      const int l = i / (NR * 64), rem = i - l * (NR * 64), r = rem >> 6, ln = rem & 63;
-      const int64_t t = t0 + l;
-      int k = ((r - r0 + NR) % NR) * 64 + ln - (lc0 + l);
-      if (k < 0) k += RS;
-      pend[m] = (i < BUF && t < p && k >= 1 && k <= bw) ? Mult[elem(t) * W + k] : 0.0;
+    for (int u = 0; u < SPT; ++u) {
+      const int sl = tid - 64 + NL * u;
+      const int r = sl >> 6, ln = sl & 63;
+      const int base = ((r - r0 + NR) % NR) * 64 + ln - lc0;
+#pragma unroll
+      for (int l = 0; l < SC; ++l) {
+        int k = base - l;
+        if (k < 0) k += RS;
+        const int64_t t = t0 + l;
+        const bool ok = sl < NR * 64 && t < p && k >= 1 && k <= bw;
+        pend[u * SC + l] = ok ? Mult[elem(t) * W + k] : 0.0;
+      }
     }
   };
   auto stage_store = [&](double* buf) {
 #pragma unroll
-    for (int m = 0; m < PER; ++m) {
-      const int i = tid - 64 + NL * m;
-      if (i < BUF) buf[i] = pend[m];
+    for (int u = 0; u < SPT; ++u) {
+      const int sl = tid - 64 + NL * u;
+      if (sl < NR * 64) {
+        const int r = sl >> 6, ln = sl & 63;
+#pragma unroll
+        for (int l = 0; l < SC; ++l) buf[(l * NR + r) * 64 + ln] = pend[u * SC + l];
+      }
     }
   };
   double reg[NR];
-  double yout = 0.0, idv = 0.0, nb = 0.0, idv_nx = 0.0, nb_nx = 0.0;
+  double idv = 0.0, nb = 0.0, idv_nx = 0.0, nb_nx = 0.0;
   // 1/L_jj of a chunk's 64 steps and the 64 elements that enter the ring at
   // its end, loaded one chunk ahead
   auto load_chunk = [&](int64_t tc0, double& iv, double& nv) {
@@ -223,12 +289,15 @@ __device__ __forceinline__ void band_sweep_t(const double* __restrict__ b, doubl
     iv = tc < p ? invd[elem(tc)] : 0.0;
     nv = tn < p ? b[elem(tn)] : 0.0;
   };
+  double bu = 0.0, pre = 0.0;  // b of the current element (final) and of the next (before this step)
   if (wave == 0) {
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const int64_t t = r * 64 + lane;
       reg[r] = t < p ? b[elem(t)] : 0.0;
     }
+    bu = readlane_f64(reg[0], 0);
+    pre = readlane_f64(reg[0], 1);
     load_chunk(0, idv_nx, nb_nx);
   } else {
     stage_load(0);
@@ -251,17 +320,21 @@ __device__ __forceinline__ void band_sweep_t(const double* __restrict__ b, doubl
         nb = nb_nx;
         load_chunk(tc0 + 64, idv_nx, nb_nx);
       }
-      band_steps_sw<NR, SC, 0>(r0, reg, yout, idv, cur, t0, lc0, p, lane);
+      band_steps_sw<NR, SC, 0, 0>(r0, lc0 / SC, reg, bu, pre, cur, lane);
       if (lc0 + SC == 64 || t0 + SC >= p) {
+        // the chunk's slots hold their final right-hand sides: y = b / L_jj
         const int64_t tc = tc0 + lane;
-        if (tc < p) out[elem(tc)] = yout;
 #pragma unroll
         for (int r = 0; r < NR; ++r)
-          if (r == r0) reg[r] = nb;
+          if (r == r0) {
+            if (tc < p) out[elem(tc)] = reg[r] * idv;
+            reg[r] = nb;
+          }
       }
     }
-    __syncthreads();
+    lds_barrier();  // the staging loads of the next sub-chunk stay in flight
   }
+  __syncthreads();
 }
 
 template <int NR>

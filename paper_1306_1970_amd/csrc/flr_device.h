@@ -85,6 +85,18 @@ __device__ inline void wg_sum4(double* v, double* lds) {
   for (int k = 0; k < 4; ++k) v[k] = (lds[k] + lds[4 + k]) + (lds[8 + k] + lds[12 + k]);
 }
 
+// Workgroup barrier that orders LDS only: each wave waits for its own LDS
+// operations (lgkmcnt 0) but not for its outstanding global loads, which may
+// stay in flight across the barrier (a plain __syncthreads waits for them,
+// which defeats loads issued ahead).  The wavefront-scope fences generate no
+// code; they keep the compiler from moving memory operations across.
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // gfx9 encoding: lgkmcnt(0), vmcnt and expcnt left at their maximum
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Affine map t -> a t + b.  compose(E, L) applies E first, then L.
 struct Aff {
   double a, b;

@@ -423,6 +423,33 @@ __global__ __launch_bounds__(kWG) void k_widen(const XT* __restrict__ X, double*
   }
 }
 
+// Column-major FP64 copy of X (n x p_pad, leading dimension n), so that
+// U = X O is a plain (N, N) GEMM: 64 x 64 tiles through LDS, reads along the
+// rows of the stored X and writes along its columns, both coalesced.
+template <typename XT>
+__global__ __launch_bounds__(kWG) void k_transpose64(const XT* __restrict__ X, double* __restrict__ Xc, int64_t n,
+                                                     int64_t ldx) {
+  __shared__ double tile[64][65];
+  const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int64_t i = i0 + r, j = j0 + tx;
+    double v = 0.0;
+    if (i < n) {
+      if constexpr (sizeof(XT) == 2)
+        v = (double)__uint_as_float(((uint32_t)X[i * ldx + j]) << 16);
+      else
+        v = (double)X[i * ldx + j];
+    }
+    tile[r][tx] = v;
+  }
+  __syncthreads();
+  for (int c = ty; c < 64; c += 4) {
+    const int64_t j = j0 + c, i = i0 + tx;
+    if (i < n) Xc[j * n + i] = tile[tx][c];
+  }
+}
+
 }  // namespace flr
 
 using namespace flr;
@@ -485,6 +512,25 @@ static flr_status grid_prepare(flr_problem h, int B, bool band) {
       default:
         hipLaunchKernelGGL(k_widen<uint16_t>, dim3(2048), dim3(kWG), 0, h->stream,
                            reinterpret_cast<const uint16_t*>(h->B.X), h->X64, cnt);
+        break;
+    }
+    GCK(hipGetLastError());
+  }
+  if (!h->X64c) {
+    GCK(hipMalloc(reinterpret_cast<void**>(&h->X64c), (size_t)D.n * (size_t)D.p_pad * sizeof(double)));
+    const dim3 tg((unsigned)(D.p_pad / 64), (unsigned)((D.n + 63) / 64));
+    switch (D.dtype) {
+      case 0:
+        hipLaunchKernelGGL(k_transpose64<double>, tg, dim3(kWG), 0, h->stream,
+                           reinterpret_cast<const double*>(h->B.X), h->X64c, D.n, D.ldx);
+        break;
+      case 1:
+        hipLaunchKernelGGL(k_transpose64<float>, tg, dim3(kWG), 0, h->stream,
+                           reinterpret_cast<const float*>(h->B.X), h->X64c, D.n, D.ldx);
+        break;
+      default:
+        hipLaunchKernelGGL(k_transpose64<uint16_t>, tg, dim3(kWG), 0, h->stream,
+                           reinterpret_cast<const uint16_t*>(h->B.X), h->X64c, D.n, D.ldx);
         break;
     }
     GCK(hipGetLastError());
@@ -651,9 +697,9 @@ static flr_status grid_run(flr_problem h, const double* l1, const double* l2, in
       t_prog = std::chrono::steady_clock::now();
       std::fprintf(stderr, "flr grid: %lld batched steps, %d of %d columns active\n", (long long)step, nact, B);
     }
-    // U = X O^T : column-major U (n x nact) = (X^T)^T O with X^T stored as p_pad x n (ld ldx)
-    if (rocblas_dgemm(gw->blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)D.n, nact,
-                      (rocblas_int)D.p_pad, &one, h->X64, (rocblas_int)D.ldx, G.O, (rocblas_int)D.p_pad, &zero, G.U,
+    // U = X O : column-major U (n x nact), X from its column-major copy
+    if (rocblas_dgemm(gw->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)D.n, nact,
+                      (rocblas_int)D.p_pad, &one, h->X64c, (rocblas_int)D.n, G.O, (rocblas_int)D.p_pad, &zero, G.U,
                       (rocblas_int)D.n) != rocblas_status_success)
       return gfail(FLR_ERR_DEVICE, "rocblas_dgemm (X O^T) failed");
     // V = X^T U : p_pad x nact
@@ -750,7 +796,7 @@ extern "C" flr_status flr_profile_grid(flr_problem h, int32_t B, int32_t reps, d
   if (!h || !avg_us || reps < 1 || B < 1) return gfail(FLR_ERR_INVALID_ARG, "flr_profile_grid: bad arguments");
   std::unique_lock<std::mutex> lk(h->busy, std::try_to_lock);
   if (!lk.owns_lock()) return gfail(FLR_ERR_BUSY, "problem handle in use by another thread");
-  if (!h->grid || h->grid->cap < B || !h->X64)
+  if (!h->grid || h->grid->cap < B || !h->X64 || !h->X64c)
     return gfail(FLR_ERR_INVALID_ARG, "flr_profile_grid: needs a completed grid solve with at least B columns");
   if (hipSetDevice(h->ctx->device) != hipSuccess) return gfail(FLR_ERR_DEVICE, "hipSetDevice failed");
   GridWork* gw = h->grid;
@@ -760,8 +806,8 @@ extern "C" flr_status flr_profile_grid(flr_problem h, int32_t B, int32_t reps, d
   hipEvent_t e[3];
   for (auto& ev : e) GCK(hipEventCreate(&ev));
   auto gemm_u = [&]() {
-    return rocblas_dgemm(gw->blas, rocblas_operation_transpose, rocblas_operation_none, (rocblas_int)D.n, B,
-                         (rocblas_int)D.p_pad, &one, h->X64, (rocblas_int)D.ldx, gw->O2, (rocblas_int)D.p_pad, &zero,
+    return rocblas_dgemm(gw->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)D.n, B,
+                         (rocblas_int)D.p_pad, &one, h->X64c, (rocblas_int)D.n, gw->O2, (rocblas_int)D.p_pad, &zero,
                          G.U, (rocblas_int)D.n);
   };
   auto gemm_v = [&]() {
