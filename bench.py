@@ -110,6 +110,7 @@ def main():
     ap.add_argument("--grid-side", type=int, default=16, help="c3: lambda values per axis (side^2 columns)")
     ap.add_argument("--grid-tol", type=float, default=1e-6, help="c3: relative objective change tolerance")
     ap.add_argument("--plain-sample", type=int, default=2, help="c3: columns also solved by the plain path")
+    ap.add_argument("--grid-max-iter", type=int, default=0, help="c3: cap on MM iterations (profiling runs only)")
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-rate", type=float, default=8.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-slots", type=int, default=4, help="concurrent solves (worker slots)")
@@ -230,13 +231,13 @@ def grid_main(args, flr):
     # workspace for B columns and the GEMM handles
     prob.solve_grid(l1, l2, tol=1e-2, max_iter=1, max_cg=2)
     t0 = time.perf_counter()
-    st, beta, res = prob.solve_grid(l1, l2, tol=args.grid_tol)
+    st, beta, res = prob.solve_grid(l1, l2, tol=args.grid_tol, max_iter=args.grid_max_iter)
     t_grid = time.perf_counter() - t0
     print("bench: grid of %d columns %.2f s, status %d, mm %d..%d, cg %d..%d" % (
         B, t_grid, st, min(r["mm_iters"] for r in res), max(r["mm_iters"] for r in res),
         min(r["cg_iters"] for r in res), max(r["cg_iters"] for r in res)), file=sys.stderr, flush=True)
     # plain path on a sample of the same columns (spread over the grid)
-    pick = np.linspace(0, B - 1, max(1, args.plain_sample)).round().astype(int)
+    pick = np.linspace(0, B - 1, args.plain_sample).round().astype(int) if args.plain_sample > 0 else []
     t_plain, gaps = 0.0, []
     for b in pick:
         t1 = time.perf_counter()
@@ -246,7 +247,7 @@ def grid_main(args, flr):
         print("bench: plain column %d lam=(%.3g,%.3g) %.2f s mm %d cg %d | grid mm %d cg %d | obj gap %.2e" % (
             b, l1[b], l2[b], time.perf_counter() - t1, s1.mm_iters, s1.cg_iters, res[b]["mm_iters"],
             res[b]["cg_iters"], gaps[-1]), file=sys.stderr, flush=True)
-    plain_rate = len(pick) / t_plain
+    plain_rate = len(pick) / t_plain if len(pick) else None
     grid_rate = B / t_grid
     ua, va = flr.flr_profile_grid(prob.h, B, 20)
     flops = 2.0 * inst.n * inst.p * B  # one GEMM
@@ -270,7 +271,8 @@ def grid_main(args, flr):
         "config": {"workload": "c3_lattice_q100_n2000_f32_grid%dx%d" % (args.grid_side, args.grid_side),
                    "n": inst.n, "p": inst.p, "columns": B, "tol": args.grid_tol,
                    "plain_solves_per_s": plain_rate, "plain_sample_columns": [int(b) for b in pick],
-                   "speedup_vs_plain": grid_rate / plain_rate, "max_objective_gap_vs_plain": max(gaps),
+                   "speedup_vs_plain": grid_rate / plain_rate if plain_rate else None,
+                   "max_objective_gap_vs_plain": max(gaps) if gaps else None,
                    "status": int(st), "mm_iters_max": max(r["mm_iters"] for r in res),
                    "cg_iters_max": max(r["cg_iters"] for r in res)},
         "roofline": {"bound": "mfma", "kernel": "dgemm_XO" if ua >= va else "dgemm_XtU", "achieved": achieved,

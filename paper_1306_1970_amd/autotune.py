@@ -14,7 +14,7 @@ import contextlib
 import json
 import os
 
-CANDIDATES = (256, 512, 1024, 2048)
+CANDIDATES = (256, 384, 512, 768, 1024, 2048)
 _ENV_A, _ENV_B = "FLR_TARGET_WG_A", "FLR_TARGET_WG_B"
 
 
