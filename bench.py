@@ -163,7 +163,7 @@ def main():
     assert all(x.status in (flr.FLR_OK, want) for x in sols), [x.status for x in sols]
 
     # live per-kernel durations (HIP events on the problem's stream)
-    a_us, b_us = flr.flr_profile_kernels(prob.h, args.profile_reps)
+    a_us, b_us, c_us = flr.flr_profile_kernels(prob.h, args.profile_reps)
     xbytes = {0: 8, 1: 4, 2: 2}[inst.dtype]
     alg_bytes = inst.n * inst.p * xbytes + 8 * (inst.p + inst.n)  # X once + operand vector + result
     dom_name, dom_us = ("gemv_a", a_us) if a_us >= b_us else ("gemv_b", b_us)
@@ -192,7 +192,8 @@ def main():
                    "objective": s.objective, "solve_effective_GBps": solve_gbs},
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "avg_us": dom_us,
-                     "algorithmic_bytes": alg_bytes, "other_kernel_us": b_us if dom_name == "gemv_a" else a_us},
+                     "algorithmic_bytes": alg_bytes, "other_kernel_us": b_us if dom_name == "gemv_a" else a_us,
+                     "block_kernel_us": c_us},
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:

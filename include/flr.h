@@ -164,11 +164,12 @@ flr_status flr_server_poll(flr_server s, uint64_t ticket, int blocking, double* 
 flr_status flr_server_stats(flr_server s, int32_t* queued, int32_t* running, size_t* bytes_in_use);
 void flr_server_destroy(flr_server s);
 
-/* Profiling: launch the rotation's row-panel kernel (X v) and column-panel
- * kernel (X^T u + M v) `reps` times each on the problem's stream, in the
- * state of a PCG step, and report their average durations in microseconds as
- * measured with HIP events on that stream.  avg_us: host, 2 entries.  The last
- * solution is left intact.  Needs a completed solve on the handle. */
+/* Profiling: launch the rotation's row-panel kernel (X v), column-panel
+ * kernel (X^T u + M v) and block kernel (PCG updates and the partitioned
+ * tridiagonal solve) `reps` times each on the problem's stream, in the state
+ * of a PCG step, and report their average durations in microseconds as
+ * measured with HIP events on that stream.  avg_us: host, 3 entries (A, B, C).
+ * The last solution is left intact.  Needs a completed solve on the handle. */
 flr_status flr_profile_kernels(flr_problem h, int32_t reps, double* avg_us);
 
 /* Profiling of the batched products of flr_solve_grid: run the two FP64 GEMMs

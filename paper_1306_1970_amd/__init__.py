@@ -220,10 +220,10 @@ def flr_server_destroy(s):
 
 
 def flr_profile_kernels(h, reps: int):
-    """Average durations (us) of the X v and X^T u kernels, HIP events on the problem's stream."""
-    out = np.zeros(2)
+    """Average durations (us) of the X v, X^T u and block kernels (HIP events on the problem's stream)."""
+    out = np.zeros(3)
     _check(lib().flr_profile_kernels(h, reps, out.ctypes.data))
-    return float(out[0]), float(out[1])
+    return float(out[0]), float(out[1]), float(out[2])
 
 
 def flr_profile_grid(h, B: int, reps: int):

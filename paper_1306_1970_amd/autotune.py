@@ -67,7 +67,7 @@ def tune(ctx, X, dtype, y, edges, lam1=0.5, lam2=1.0, candidates=CANDIDATES, rep
         with launch_shape(cand, cand):
             prob = Problem(ctx, X, dtype, y, edges)
         prob.solve(lam1, lam2, tol=1e-6, max_iter=2)
-        a_us, b_us = flr_profile_kernels(prob.h, reps)
+        a_us, b_us, _ = flr_profile_kernels(prob.h, reps)
         prob.close()
         times["a"][cand] = a_us
         times["b"][cand] = b_us

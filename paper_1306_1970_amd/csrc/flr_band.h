@@ -32,7 +32,7 @@ constexpr int kBandMaxW = 1025;   // widest band the sweeps handle (NR = 17 ring
 // current one plus the 64 of the chunk being consumed.
 __host__ __device__ inline int band_nr(int W) {
   const int need = (W + 63 + 63) / 64;
-  const int opts[] = {2, 3, 4, 5, 6, 8, 12, 17};
+  const int opts[] = {2, 3, 5, 8, 17};  // a few ring sizes keep the code (and compile time) small
   for (int o : opts)
     if (o >= need) return o;
   return 0;
@@ -173,27 +173,27 @@ __device__ inline double readlane_f64(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-// SC steps of the sweep by wave 0: sub-chunk SUB of the chunk held in ring
-// register R0 (elements t0 .. t0 + SC - 1, lanes SUB*SC ...).  The staged
-// multipliers already include 1/L_jj.  The dependent chain is one fma per
-// step, on values every lane holds: bu = b_j (final), and the next element's
-// final value b_{j+1} = pre - m b_j, where pre is b_{j+1} after the steps
-// before j (read from its lane one step early) and m its multiplier at step
-// j (a broadcast LDS read).  The ring update - one fma per register - and
-// those reads stay off that chain.
-template <int NR, int SC, int R0, int SUB>
+// SC steps of the sweep by wave 0: elements t0 .. t0 + SC - 1, held in
+// lanes lc0 .. lc0 + SC - 1 of ring register R0.  The staged multipliers
+// already include 1/L_jj.  The dependent chain is one fma per step, on values
+// every lane holds: bu = b_j (final), and the next element's final value
+// b_{j+1} = pre - m b_j, where pre is b_{j+1} after the steps before j (read
+// from its lane one step early) and m its multiplier at step j (a broadcast
+// LDS read).  The ring update - one fma per register - and those reads stay
+// off that chain.  Elements j + 1, j + 2 live in register R0 or, in the last
+// two steps of a chunk, in the next ring register R1.
+template <int NR, int SC, int R0>
 __device__ __forceinline__ void band_steps(double (&reg)[NR], double& bu, double& pre, const double* __restrict__ buf,
-                                           int lane) {
-  constexpr int LC0 = SUB * SC;
+                                           int lc0, int lane) {
+  constexpr int R1 = (R0 + 1) % NR;
   double mc[NR], mn[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) mc[r] = buf[r * 64 + lane];
 #pragma unroll
   for (int l = 0; l < SC; ++l) {
-    // ring position of elements j + 1 and j + 2 (compile time)
-    const int s1 = R0 * 64 + LC0 + l + 1, s2 = s1 + 1;
-    const int r1 = (s1 / 64) % NR, ln1 = s1 % 64;
-    const int r2 = (s2 / 64) % NR, ln2 = s2 % 64;
+    const int lc = lc0 + l;
+    const int ln1 = (lc + 1) & 63, ln2 = (lc + 2) & 63;
+    const int r1 = lc + 1 < 64 ? R0 : R1;
     if (l + 1 < SC) {
 #pragma unroll
       for (int r = 0; r < NR; ++r) mn[r] = buf[((l + 1) * NR + r) * 64 + lane];
@@ -201,7 +201,7 @@ __device__ __forceinline__ void band_steps(double (&reg)[NR], double& bu, double
     const double m1 = buf[(l * NR + r1) * 64 + ln1];  // broadcast
 #pragma unroll
     for (int r = 0; r < NR; ++r) reg[r] = fma(-mc[r], bu, reg[r]);
-    const double pre2 = readlane_f64(reg[r2], ln2);
+    const double pre2 = readlane_f64(lc + 2 < 64 ? reg[R0] : reg[R1], ln2);
     bu = fma(-m1, bu, pre);
     pre = pre2;
 #pragma unroll
@@ -209,18 +209,14 @@ __device__ __forceinline__ void band_steps(double (&reg)[NR], double& bu, double
   }
 }
 
-template <int NR, int SC, int R0, int SUB>
-__device__ __forceinline__ void band_steps_sw(int r0, int sub, double (&reg)[NR], double& bu, double& pre,
-                                              const double* buf, int lane) {
+template <int NR, int SC, int R0>
+__device__ __forceinline__ void band_steps_sw(int r0, double (&reg)[NR], double& bu, double& pre, const double* buf,
+                                              int lc0, int lane) {
   if constexpr (R0 < NR) {
-    if constexpr (SUB < 64 / SC) {
-      if (r0 == R0 && sub == SUB)
-        band_steps<NR, SC, R0, SUB>(reg, bu, pre, buf, lane);
-      else
-        band_steps_sw<NR, SC, R0, SUB + 1>(r0, sub, reg, bu, pre, buf, lane);
-    } else {
-      band_steps_sw<NR, SC, R0 + 1, 0>(r0, sub, reg, bu, pre, buf, lane);
-    }
+    if (r0 == R0)
+      band_steps<NR, SC, R0>(reg, bu, pre, buf, lc0, lane);
+    else
+      band_steps_sw<NR, SC, R0 + 1>(r0, reg, bu, pre, buf, lc0, lane);
   }
 }
 
@@ -320,7 +316,7 @@ __device__ __forceinline__ void band_sweep_t(const double* __restrict__ b, doubl
         nb = nb_nx;
         load_chunk(tc0 + 64, idv_nx, nb_nx);
       }
-      band_steps_sw<NR, SC, 0, 0>(r0, lc0 / SC, reg, bu, pre, cur, lane);
+      band_steps_sw<NR, SC, 0>(r0, reg, bu, pre, cur, lc0, lane);
       if (lc0 + SC == 64 || t0 + SC >= p) {
         // the chunk's slots hold their final right-hand sides: y = b / L_jj
         const int64_t tc = tc0 + lane;
@@ -353,11 +349,8 @@ __device__ __forceinline__ void band_solve(const double* r, double* tmp, double*
   switch (band_nr(W)) {
     case 2: band_solve_nr<2>(r, tmp, z, Lb, LbT, invd, p, W, lds); break;
     case 3: band_solve_nr<3>(r, tmp, z, Lb, LbT, invd, p, W, lds); break;
-    case 4: band_solve_nr<4>(r, tmp, z, Lb, LbT, invd, p, W, lds); break;
     case 5: band_solve_nr<5>(r, tmp, z, Lb, LbT, invd, p, W, lds); break;
-    case 6: band_solve_nr<6>(r, tmp, z, Lb, LbT, invd, p, W, lds); break;
     case 8: band_solve_nr<8>(r, tmp, z, Lb, LbT, invd, p, W, lds); break;
-    case 12: band_solve_nr<12>(r, tmp, z, Lb, LbT, invd, p, W, lds); break;
     default: band_solve_nr<17>(r, tmp, z, Lb, LbT, invd, p, W, lds); break;
   }
 }

@@ -551,11 +551,29 @@ flr_status flr_profile_kernels(flr_problem h, int32_t reps, double* avg_us) {
   HIP_OR_FAIL(hipEventRecord(e2, h->stream));
   HIP_OR_FAIL(hipStreamSynchronize(h->stream));
   HIP_OR_FAIL(hipEventElapsedTime(&ms_b, e1, e2));
+  // C in the same PCG-step state: it moves x and r, so both are saved first
+  // and restored afterwards (the last solution stays intact)
+  double* save = nullptr;
+  const size_t vb = (size_t)h->D.p_pad * sizeof(double);
+  HIP_OR_FAIL(hipMalloc(reinterpret_cast<void**>(&save), 2 * vb));
+  HIP_OR_FAIL(hipMemcpyAsync(save, h->B.x, vb, hipMemcpyDeviceToDevice, h->stream));
+  HIP_OR_FAIL(hipMemcpyAsync(save + h->D.p_pad, h->B.r, vb, hipMemcpyDeviceToDevice, h->stream));
+  HIP_OR_FAIL(hipMemcpyAsync(h->B.st, hs, 2 * sizeof(State), hipMemcpyHostToDevice, h->stream));
+  float ms_c = 0.f;
+  HIP_OR_FAIL(hipEventRecord(e1, h->stream));
+  for (int i = 0; i < reps; ++i) HIP_OR_FAIL(launch_rotation(h->D, h->B, 0, 2, h->stream, false));
+  HIP_OR_FAIL(hipEventRecord(e2, h->stream));
+  HIP_OR_FAIL(hipMemcpyAsync(h->B.x, save, vb, hipMemcpyDeviceToDevice, h->stream));
+  HIP_OR_FAIL(hipMemcpyAsync(h->B.r, save + h->D.p_pad, vb, hipMemcpyDeviceToDevice, h->stream));
+  HIP_OR_FAIL(hipStreamSynchronize(h->stream));
+  HIP_OR_FAIL(hipEventElapsedTime(&ms_c, e1, e2));
+  (void)hipFree(save);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipEventDestroy(e2);
   avg_us[0] = 1000.0 * ms_a / reps;
   avg_us[1] = 1000.0 * ms_b / reps;
+  avg_us[2] = 1000.0 * ms_c / reps;
   return FLR_OK;
 }
 

@@ -208,7 +208,8 @@ __global__ __launch_bounds__(kWG) void k_col(GridDev G) {
   const double* V = G.V + (int64_t)slot * P;
   const double* U = G.U + (int64_t)slot * G.n;
 
-  if (s.phase == PH_CG) {
+  const bool cg = s.phase == PH_CG;
+  if (cg) {
     // q = X^T X p + M p (kept in z), p^T q
     double part = 0.0;
     for (int64_t j = tid; j < p; j += kWG) {
@@ -232,122 +233,93 @@ __global__ __launch_bounds__(kWG) void k_col(GridDev G) {
       r[j] = fma(-nu, z[j], r[j]);
     }
     __syncthreads();
-    if (use_band)
-      band_solve(r, G.g + off, z, Lbb, LbTb, G.invD + off, p, W, bl);
-    else
-      col_tri_solve(r, G.L + off, G.invD + off, G.g + off, z, p, lds, sh2);
-    double rzp = 0.0, rrp = 0.0;
-    for (int64_t j = tid; j < p; j += kWG) {
-      rzp = fma(r[j], z[j], rzp);
-      rrp = fma(r[j], r[j], rrp);
-    }
-    const double rz = wg_sum(rzp, lds);
-    const double rr = wg_sum(rrp, lds);
-    const double rn = sqrt(rr) / prm.cnorm;
-    s.cg_iter += 1;
-    s.cg_total += 1;
-    s.rel_res = rn;
-    const bool done = !(rn > prm.inner_tol) || s.cg_iter >= prm.max_cg;
-    if (done) {
-      s.phase = PH_END;
-      for (int64_t j = tid; j < P; j += kWG) O[j] = j < p ? x[j] : 0.0;
-    } else {
-      const double gamma = rz / s.rz;
-      for (int64_t j = tid; j < p; j += kWG) {
-        const double v = fma(gamma, pv[j], z[j]);
-        pv[j] = v;
-        O[j] = v;
-      }
-      s.rz = rz;
-    }
-    if (tid == 0) G.st[b] = s;
-    return;
-  }
-
-  // ---- MM boundary: U = X x, V = X^T X x for this column ----
-  double lp = 0.0;
-  for (int64_t i = tid; i < G.n; i += kWG) {
-    const double dlt = G.y[i] - U[i];
-    lp = fma(dlt, dlt, lp);
-  }
-  double pp = 0.0;
-  for (int64_t j = tid; j < p; j += kWG) {
-    const double xj = x[j];
-    double pen2 = 0.0;
-    for (int q = G.rowptr[j]; q < G.rowptr[j + 1]; ++q) {
-      const int k = G.col[q];
-      if (k > j) pen2 += fabs(xj - x[k]);
-    }
-    pp += l1 * fabs(xj) + l2 * pen2;
-  }
-  const double loss = wg_sum(lp, lds);
-  const double pen = wg_sum(pp, lds);
-  const double f_new = 0.5 * loss + pen;
-  s.f_new = f_new;
-  bool finish = false;
-  if (!isfinite(f_new)) {
-    s.status = ST_NUMERICAL;
-    finish = true;
-  } else if (s.first) {
-    s.first = 0;
   } else {
-    s.mm_iter += 1;
-    const double re = s.f_old != 0.0 ? fabs(f_new - s.f_old) / fabs(s.f_old) : fabs(f_new - s.f_old);
-    s.rel_change = re;
-    if (re <= prm.tol) {
-      s.status = ST_OK;
-      finish = true;
-    } else if (s.mm_iter >= prm.max_iter) {
-      s.status = ST_MAX_ITER;
-      finish = true;
+    // ---- MM boundary: U = X x, V = X^T X x for this column ----
+    double lp = 0.0;
+    for (int64_t i = tid; i < G.n; i += kWG) {
+      const double dlt = G.y[i] - U[i];
+      lp = fma(dlt, dlt, lp);
     }
-  }
-  if (finish) {
-    s.phase = PH_DONE;
-    for (int64_t j = tid; j < P; j += kWG) O[j] = 0.0;
-    if (tid == 0) G.st[b] = s;
-    return;
-  }
-  s.f_old = f_new;
-  s.cg_iter = 0;
-  // reweighting (majorizer at the current iterate) and the tridiagonal part of M
-  double* a = G.a + off;
-  double* w = G.w + (int64_t)b * G.nnz;
-  double* d = G.d + off;
-  double* e = G.e + off;
-  for (int64_t j = tid; j < p; j += kWG) {
-    const double xj = x[j];
-    const double aj = 1.0 / (fabs(xj) + prm.eps);
-    a[j] = aj;
-    double wsum = 0.0, ej = 0.0;
-    for (int q = G.rowptr[j]; q < G.rowptr[j + 1]; ++q) {
-      const int k = G.col[q];
-      const double wq = 1.0 / (fabs(xj - x[k]) + prm.eps);
-      w[q] = wq;
-      wsum += wq;
-      if (k == j - 1 && !s.jacobi) ej = -l2 * wq;
+    double pp = 0.0;
+    for (int64_t j = tid; j < p; j += kWG) {
+      const double xj = x[j];
+      double pen2 = 0.0;
+      for (int q = G.rowptr[j]; q < G.rowptr[j + 1]; ++q) {
+        const int k = G.col[q];
+        if (k > j) pen2 += fabs(xj - x[k]);
+      }
+      pp += l1 * fabs(xj) + l2 * pen2;
     }
-    double dj = l1 * aj + l2 * wsum;
-    if (s.jacobi) dj += G.s[j];
-    d[j] = dj;
-    e[j] = ej;
-  }
-  __syncthreads();
-  if (use_band) {
-    band_assemble(d, G.rowptr, G.col, w, l2, p, W, Lbb);
-    if (!band_factor(Lbb, LbTb, G.invD + off, p, W, bl)) {
+    const double loss = wg_sum(lp, lds);
+    const double pen = wg_sum(pp, lds);
+    const double f_new = 0.5 * loss + pen;
+    s.f_new = f_new;
+    bool finish = false;
+    if (!isfinite(f_new)) {
       s.status = ST_NUMERICAL;
+      finish = true;
+    } else if (s.first) {
+      s.first = 0;
+    } else {
+      s.mm_iter += 1;
+      const double re = s.f_old != 0.0 ? fabs(f_new - s.f_old) / fabs(s.f_old) : fabs(f_new - s.f_old);
+      s.rel_change = re;
+      if (re <= prm.tol) {
+        s.status = ST_OK;
+        finish = true;
+      } else if (s.mm_iter >= prm.max_iter) {
+        s.status = ST_MAX_ITER;
+        finish = true;
+      }
+    }
+    if (finish) {
       s.phase = PH_DONE;
       for (int64_t j = tid; j < P; j += kWG) O[j] = 0.0;
       if (tid == 0) G.st[b] = s;
       return;
     }
-  } else {
-    col_factor(d, e, G.L + off, G.invD + off, p, sh4);
+    s.f_old = f_new;
+    s.cg_iter = 0;
+    // reweighting (majorizer at the current iterate) and the tridiagonal part of M
+    double* a = G.a + off;
+    double* w = G.w + (int64_t)b * G.nnz;
+    double* d = G.d + off;
+    double* e = G.e + off;
+    for (int64_t j = tid; j < p; j += kWG) {
+      const double xj = x[j];
+      const double aj = 1.0 / (fabs(xj) + prm.eps);
+      a[j] = aj;
+      double wsum = 0.0, ej = 0.0;
+      for (int q = G.rowptr[j]; q < G.rowptr[j + 1]; ++q) {
+        const int k = G.col[q];
+        const double wq = 1.0 / (fabs(xj - x[k]) + prm.eps);
+        w[q] = wq;
+        wsum += wq;
+        if (k == j - 1 && !s.jacobi) ej = -l2 * wq;
+      }
+      double dj = l1 * aj + l2 * wsum;
+      if (s.jacobi) dj += G.s[j];
+      d[j] = dj;
+      e[j] = ej;
+    }
+    __syncthreads();
+    if (use_band) {
+      band_assemble(d, G.rowptr, G.col, w, l2, p, W, Lbb);
+      if (!band_factor(Lbb, LbTb, G.invD + off, p, W, bl)) {
+        s.status = ST_NUMERICAL;
+        s.phase = PH_DONE;
+        for (int64_t j = tid; j < P; j += kWG) O[j] = 0.0;
+        if (tid == 0) G.st[b] = s;
+        return;
+      }
+    } else {
+      col_factor(d, e, G.L + off, G.invD + off, p, sh4);
+    }
+    // r0 = c - (X^T X + M) x
+    for (int64_t j = tid; j < p; j += kWG) r[j] = G.c[j] - (V[j] + col_apply_m(G, b, j, x, l1, l2));
+    __syncthreads();
   }
-  // r0 = c - (X^T X + M) x
-  for (int64_t j = tid; j < p; j += kWG) r[j] = G.c[j] - (V[j] + col_apply_m(G, b, j, x, l1, l2));
-  __syncthreads();
+  // z = M^-1 r (one call site for both branches)
   if (use_band)
     band_solve(r, G.g + off, z, Lbb, LbTb, G.invD + off, p, W, bl);
   else
@@ -361,17 +333,35 @@ __global__ __launch_bounds__(kWG) void k_col(GridDev G) {
   const double rr = wg_sum(rrp, lds);
   const double rn = sqrt(rr) / prm.cnorm;
   s.rel_res = rn;
-  s.rz = rz;
-  const bool done = !(rn > prm.inner_tol) || prm.max_cg <= 0;
-  if (done) {
-    s.phase = PH_END;
-    for (int64_t j = tid; j < P; j += kWG) O[j] = j < p ? x[j] : 0.0;
+  if (cg) {
+    s.cg_iter += 1;
+    s.cg_total += 1;
+    const bool done = !(rn > prm.inner_tol) || s.cg_iter >= prm.max_cg;
+    if (done) {
+      s.phase = PH_END;
+      for (int64_t j = tid; j < P; j += kWG) O[j] = j < p ? x[j] : 0.0;
+    } else {
+      const double gamma = rz / s.rz;
+      for (int64_t j = tid; j < p; j += kWG) {
+        const double v = fma(gamma, pv[j], z[j]);
+        pv[j] = v;
+        O[j] = v;
+      }
+      s.rz = rz;
+    }
   } else {
-    s.phase = PH_CG;
-    for (int64_t j = tid; j < P; j += kWG) {
-      const double v = j < p ? z[j] : 0.0;
-      pv[j] = v;
-      O[j] = v;
+    s.rz = rz;
+    const bool done = !(rn > prm.inner_tol) || prm.max_cg <= 0;
+    if (done) {
+      s.phase = PH_END;
+      for (int64_t j = tid; j < P; j += kWG) O[j] = j < p ? x[j] : 0.0;
+    } else {
+      s.phase = PH_CG;
+      for (int64_t j = tid; j < P; j += kWG) {
+        const double v = j < p ? z[j] : 0.0;
+        pv[j] = v;
+        O[j] = v;
+      }
     }
   }
   if (tid == 0) G.st[b] = s;

@@ -321,3 +321,20 @@ def test_mixed_precision_objective_gap(flr, ctx, dtype):
     assert abs(gap) <= 1e-6
     # the reported objective is the FP64 objective of the returned beta
     assert abs(mixed.objective - f_mixed) <= 1e-11 * f_mixed
+
+
+def test_profiling_leaves_solution_intact(flr, ctx):
+    # flr_profile_kernels runs the rotation's kernels in a synthetic PCG state; the handle's last
+    # solution (the warm start of use_last) must be what it was
+    inst = flrgen.small_instance(60, 700, "chain", dtype=flrgen.F32, seed=14)
+    a = flr.Problem.from_instance(ctx, inst)
+    a.solve(0.2, 0.4, tol=1e-6)
+    us = flr.flr_profile_kernels(a.h, 5)
+    assert len(us) == 3 and all(u > 0 for u in us)
+    sa = a.solve(0.2, 0.4, tol=1e-6, use_last=1, max_iter=2)
+    a.close()
+    b = flr.Problem.from_instance(ctx, inst)
+    b.solve(0.2, 0.4, tol=1e-6)
+    sb = b.solve(0.2, 0.4, tol=1e-6, use_last=1, max_iter=2)
+    b.close()
+    assert np.array_equal(sa.beta, sb.beta)
