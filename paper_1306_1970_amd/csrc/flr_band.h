@@ -236,44 +236,33 @@ __device__ __forceinline__ void band_sweep_t(const double* __restrict__ b, doubl
   const int bw = W - 1;
   const int64_t nsub = (p + SC - 1) / SC;
   auto elem = [&](int64_t t) { return fwd ? t : p - 1 - t; };
-  // Waves 1..3 stage sub-chunk s.  Each of their threads owns fixed ring
-  // slots (register r, lane ln) and walks the SC steps: the distance k from
-  // the step's element to the slot's element drops by one per step, so the
-  // multiplier's address advances by W - 1.  All loads of a thread are
-  // issued before any is written to LDS, one sub-chunk early (into pend), so
-  // their latency hides behind wave 0's steps.
+  // Waves 1..3 stage sub-chunk s: thread i of the 192 takes elements i,
+  // i + 192, ... of the sub-chunk's SC x NR x 64 multipliers (step-major, then
+  // ring register, then lane, the order wave 0 reads them).  All PER loads of
+  // a thread are issued before any is written to LDS, one sub-chunk early
+  // (into pend), so their latency hides behind wave 0's steps.
   constexpr int NL = kWG - 64;
-  constexpr int SPT = (NR * 64 + NL - 1) / NL;  // ring slots per staging thread
-  constexpr int PER = SC * SPT;
+  constexpr int PER = (BUF + NL - 1) / NL;
   double pend[PER];
   auto stage_load = [&](int64_t s) {
     const int64_t t0 = s * SC;
     const int r0 = (int)((t0 / 64) % NR);
     const int lc0 = (int)(t0 % 64);
 #pragma unroll
-    for (int u = 0; u < SPT; ++u) {
-      const int sl = tid - 64 + NL * u;
-      const int r = sl >> 6, ln = sl & 63;
-      const int base = ((r - r0 + NR) % NR) * 64 + ln - lc0;
-#pragma unroll
-      for (int l = 0; l < SC; ++l) {
-        int k = base - l;
-        if (k < 0) k += RS;
-        const int64_t t = t0 + l;
-        const bool ok = sl < NR * 64 && t < p && k >= 1 && k <= bw;
-        pend[u * SC + l] = ok ? Mult[elem(t) * W + k] : 0.0;
-      }
+    for (int m = 0; m < PER; ++m) {
+      const int i = tid - 64 + NL * m;
+      const int l = i / (NR * 64), rem = i - l * (NR * 64), r = rem >> 6, ln = rem & 63;
+      const int64_t t = t0 + l;
+      int k = ((r - r0 + NR) % NR) * 64 + ln - (lc0 + l);
+      if (k < 0) k += RS;
+      pend[m] = (i < BUF && t < p && k >= 1 && k <= bw) ? Mult[elem(t) * W + k] : 0.0;
     }
   };
   auto stage_store = [&](double* buf) {
 #pragma unroll
-    for (int u = 0; u < SPT; ++u) {
-      const int sl = tid - 64 + NL * u;
-      if (sl < NR * 64) {
-        const int r = sl >> 6, ln = sl & 63;
-#pragma unroll
-        for (int l = 0; l < SC; ++l) buf[(l * NR + r) * 64 + ln] = pend[u * SC + l];
-      }
+    for (int m = 0; m < PER; ++m) {
+      const int i = tid - 64 + NL * m;
+      if (i < BUF) buf[i] = pend[m];
     }
   };
   double reg[NR];
