@@ -144,6 +144,20 @@ flr_status flr_solve_ex(flr_problem h, double lambda1, double lambda2, double to
 flr_status flr_solve_grid(flr_problem h, const double* lambda1, const double* lambda2, int32_t B, double tol,
                           const flr_solve_opts* opts, double* beta_out, flr_result* res);
 
+/* Ragged batch: `count` solves on distinct, idle problem handles of any
+ * sizes and graphs (n_i, p_i, E_i), each with its own (lambda1[i],
+ * lambda2[i]), in one call.  One host thread keeps two captured rotations of
+ * every solve in flight on that problem's own stream, so the solves' kernels
+ * overlap on the device, and each result is the one the solo flr_solve_ex
+ * gives (same kernels, same reduction trees).  beta_out: nullable array of
+ * `count` pointers (host or device, length p_i each, each nullable); res:
+ * nullable, `count` entries.  Returns FLR_OK when every solve converged, else
+ * the first failing status; FLR_ERR_INVALID_ARG for a repeated handle,
+ * FLR_ERR_BUSY when a handle is in use. */
+flr_status flr_solve_batch(const flr_problem* problems, int32_t count, const double* lambda1,
+                           const double* lambda2, double tol, const flr_solve_opts* opts, double* const* beta_out,
+                           flr_result* res);
+
 /* Device footprint of a problem in bytes (what serving admission charges). */
 flr_status flr_problem_footprint(flr_problem h, size_t* bytes);
 int64_t flr_problem_n(flr_problem h);

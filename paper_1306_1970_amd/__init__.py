@@ -29,7 +29,7 @@ EXPORTS = [
     "flr_default_opts", "flr_ctx_create", "flr_ctx_destroy", "flr_create", "flr_destroy", "flr_solve",
     "flr_solve_ex", "flr_solve_grid", "flr_problem_footprint", "flr_problem_n", "flr_problem_p", "flr_problem_m",
     "flr_server_create", "flr_server_submit", "flr_server_poll", "flr_server_stats", "flr_server_destroy",
-    "flr_profile_kernels", "flr_profile_grid", "flr_status_string", "flr_last_error",
+    "flr_profile_kernels", "flr_profile_grid", "flr_status_string", "flr_last_error", "flr_solve_batch",
 ]
 
 
@@ -84,6 +84,7 @@ def lib():
         L.flr_server_destroy.argtypes = [vp]
         L.flr_profile_kernels.argtypes = [vp, i32, vp]
         L.flr_profile_grid.argtypes = [vp, i32, i32, vp]
+        L.flr_solve_batch.argtypes = [vp, i32, vp, vp, d, C.POINTER(flr_solve_opts), vp, vp]
         L.flr_status_string.argtypes = [C.c_int]
         L.flr_status_string.restype = C.c_char_p
         L.flr_last_error.restype = C.c_char_p
@@ -224,6 +225,23 @@ def flr_profile_kernels(h, reps: int):
     out = np.zeros(3)
     _check(lib().flr_profile_kernels(h, reps, out.ctypes.data))
     return float(out[0]), float(out[1]), float(out[2])
+
+
+def flr_solve_batch(problems, lambda1, lambda2, tol, opts=None, betas=None):
+    """Ragged batch: one call solves every (problem, lambda1, lambda2); betas: list of arrays (or None)."""
+    k = len(problems)
+    hs = (C.c_void_p * k)(*[p.h if hasattr(p, "h") else p for p in problems])
+    l1 = np.ascontiguousarray(lambda1, dtype=np.float64)
+    l2 = np.ascontiguousarray(lambda2, dtype=np.float64)
+    res = (flr_result * k)()
+    outs = None
+    if betas is not None:
+        outs = (C.c_void_p * k)(*[_ptr(b) for b in betas])
+    o = opts if opts is not None else default_opts()
+    st = lib().flr_solve_batch(hs, k, l1.ctypes.data, l2.ctypes.data, tol, C.byref(o),
+                               C.cast(outs, C.c_void_p) if outs is not None else None, C.cast(res, C.c_void_p))
+    _check(st, ok=(FLR_OK, FLR_ERR_MAX_ITER, FLR_ERR_NUMERICAL))
+    return st, list(res)
 
 
 def flr_profile_grid(h, B: int, reps: int):

@@ -126,10 +126,20 @@ flr_status validate_lambdas(double l1, double l2, double tol) {
   return FLR_OK;
 }
 
-// One solve on the problem's stream; beta_out host or device (or nullptr).
-flr_status run_solve(flr_problem h, double l1, double l2, double tol, const flr_solve_opts* o, double* beta_out,
-                     flr_result* res) {
-  auto t0 = std::chrono::steady_clock::now();
+// One solve in flight: the problem, its captured rotation and the launch count.
+struct SolveRun {
+  flr_problem h = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int64_t max_launches = 0, launched = 0;
+  int in_flight = 0;
+  bool done = false;
+  std::chrono::steady_clock::time_point t0;
+};
+
+// Parameters, warm start, initial state and the captured rotation of a solve.
+flr_status solve_begin(flr_problem h, double l1, double l2, double tol, const flr_solve_opts* o, SolveRun& run) {
+  run.t0 = std::chrono::steady_clock::now();
+  run.h = h;
   flr_solve_opts dflt;
   flr_default_opts(&dflt);
   if (!o) o = &dflt;
@@ -164,55 +174,67 @@ flr_status run_solve(flr_problem h, double l1, double l2, double tol, const flr_
     if (is_device_ptr(o->warm_start)) {
       warm = o->warm_start;
     } else {
+      // staged in the residual buffer; k_init reads warm[j] before clearing r[j] in the same thread
       HIP_OR_FAIL(hipMemcpyAsync(h->B.r, o->warm_start, D.p * sizeof(double), hipMemcpyHostToDevice, h->stream));
-      warm = h->B.r;  // staged in the residual buffer; k_init reads it before clearing
+      warm = h->B.r;
     }
     use_warm = 1;
   } else if (o->use_last && h->has_solution) {
     warm = h->B.x;
     use_warm = 1;
   }
-  if (use_warm && warm == h->B.r) {
-    // k_init clears r after reading warm[j] in the same thread: safe element-wise
-  }
   HIP_OR_FAIL(launch_init(D, h->B, warm, use_warm, h->stream));
   const bool mixed = P.mixed != 0;
   const bool band = P.band != 0;
   flr_status gs = build_graph(h, mixed, band);
   if (gs != FLR_OK) return gs;
-  hipGraphExec_t gexec = h->gexec[mixed][band];
+  run.gexec = h->gexec[mixed][band];
+  run.max_launches = ((int64_t)P.max_iter * ((int64_t)P.max_cg + 2) + 2) / kRounds + 4;
+  run.launched = 0;
+  run.in_flight = 0;
+  run.done = false;
+  return FLR_OK;
+}
 
-  // launch the captured rotation until the state machine reports done; keep
-  // one launch in flight beyond the one being polled
-  const int64_t max_launches = ((int64_t)P.max_iter * ((int64_t)P.max_cg + 2) + 2) / kRounds + 4;
-  int64_t launched = 0;
-  bool done = false;
-  State fin{};
-  // FLR_PROGRESS=1: a line on stderr every few seconds from the polling loop
-  const char* prog_env = std::getenv("FLR_PROGRESS");
-  const bool progress = prog_env && prog_env[0] && prog_env[0] != '0';
-  auto t_prog = std::chrono::steady_clock::now();
-  while (!done) {
-    if (launched >= max_launches) return fail(FLR_ERR_DEVICE, "solve did not terminate within its launch bound");
-    const int slot = (int)(launched & 1);
-    HIP_OR_FAIL(hipGraphLaunch(gexec, h->stream));
+// Keeps two launches of the captured rotation in flight: launches one when
+// fewer are, else looks at the older one (waiting for it when blocking) and
+// marks the solve done once the state it left says so.  *progress: whether
+// anything was launched or retired.
+flr_status solve_advance(SolveRun& run, bool blocking, bool* progress) {
+  flr_problem h = run.h;
+  *progress = false;
+  if (!run.done && run.in_flight < 2) {
+    if (run.launched >= run.max_launches) return fail(FLR_ERR_DEVICE, "solve did not terminate within its launch bound");
+    const int slot = (int)(run.launched & 1);
+    HIP_OR_FAIL(hipGraphLaunch(run.gexec, h->stream));
     HIP_OR_FAIL(hipMemcpyAsync(&h->h_state[slot], &h->B.st[0], sizeof(State), hipMemcpyDeviceToHost, h->stream));
     HIP_OR_FAIL(hipEventRecord(h->ev[slot], h->stream));
-    ++launched;
-    if (launched >= 2) {
-      const int prev = (int)((launched - 2) & 1);
-      HIP_OR_FAIL(hipEventSynchronize(h->ev[prev]));
-      if (h->h_state[prev].phase == PH_DONE) done = true;
-      if (progress && std::chrono::steady_clock::now() - t_prog > std::chrono::seconds(5)) {
-        t_prog = std::chrono::steady_clock::now();
-        std::fprintf(stderr, "flr solve: MM %d, PCG steps %lld, f %.12g\n", h->h_state[prev].mm_iter,
-                     (long long)h->h_state[prev].cg_total, h->h_state[prev].f_new);
-      }
-    }
+    ++run.launched;
+    ++run.in_flight;
+    *progress = true;
+    if (run.in_flight < 2) return FLR_OK;
   }
+  if (run.in_flight == 0) return FLR_OK;
+  const int oldest = (int)((run.launched - run.in_flight) & 1);
+  if (blocking) {
+    HIP_OR_FAIL(hipEventSynchronize(h->ev[oldest]));
+  } else {
+    const hipError_t q = hipEventQuery(h->ev[oldest]);
+    if (q == hipErrorNotReady) return FLR_OK;
+    HIP_OR_FAIL(q);
+  }
+  --run.in_flight;
+  *progress = true;
+  if (h->h_state[oldest].phase == PH_DONE) run.done = true;
+  return FLR_OK;
+}
+
+// After the solve is done: outputs and status.
+flr_status solve_end(SolveRun& run, double* beta_out, flr_result* res) {
+  flr_problem h = run.h;
   HIP_OR_FAIL(hipStreamSynchronize(h->stream));
-  fin = h->h_state[(launched - 1) & 1];
-  if (beta_out) HIP_OR_FAIL(hipMemcpy(beta_out, h->B.x, D.p * sizeof(double), hipMemcpyDefault));
+  const State fin = h->h_state[(run.launched - 1) & 1];
+  if (beta_out) HIP_OR_FAIL(hipMemcpy(beta_out, h->B.x, h->D.p * sizeof(double), hipMemcpyDefault));
   h->has_solution = true;
   flr_status st = fin.status == ST_OK ? FLR_OK : fin.status == ST_MAX_ITER ? FLR_ERR_MAX_ITER : FLR_ERR_NUMERICAL;
   if (res) {
@@ -222,17 +244,40 @@ flr_status run_solve(flr_problem h, double l1, double l2, double tol, const flr_
     res->cg_iters = fin.cg_total;
     res->mm_iters = fin.mm_iter;
     res->status = st;
-    res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - run.t0).count();
   }
   if (st == FLR_ERR_NUMERICAL) g_last_error = "non-finite value or CG breakdown inside the solve";
   if (st == FLR_ERR_MAX_ITER) g_last_error = "MM iteration cap reached";
   return st;
 }
 
+// One solve on the problem's stream; beta_out host or device (or nullptr).
+flr_status run_solve(flr_problem h, double l1, double l2, double tol, const flr_solve_opts* o, double* beta_out,
+                     flr_result* res) {
+  SolveRun run;
+  flr_status st = solve_begin(h, l1, l2, tol, o, run);
+  if (st != FLR_OK) return st;
+  // FLR_PROGRESS=1: a line on stderr every few seconds from the polling loop
+  const char* prog_env = std::getenv("FLR_PROGRESS");
+  const bool progress = prog_env && prog_env[0] && prog_env[0] != '0';
+  auto t_prog = std::chrono::steady_clock::now();
+  while (!run.done) {
+    bool moved = false;
+    st = solve_advance(run, true, &moved);
+    if (st != FLR_OK) return st;
+    if (progress && std::chrono::steady_clock::now() - t_prog > std::chrono::seconds(5)) {
+      t_prog = std::chrono::steady_clock::now();
+      const State& hs = h->h_state[(run.launched - run.in_flight - 1) & 1];
+      std::fprintf(stderr, "flr solve: MM %d, PCG steps %lld, f %.12g\n", hs.mm_iter, (long long)hs.cg_total,
+                   hs.f_new);
+    }
+  }
+  return solve_end(run, beta_out, res);
+}
+
 }  // namespace
 
 namespace flr {
-// Entry used by the serving loop: the caller already holds the handle.
 flr_status solve_locked(flr_problem h, double l1, double l2, double tol, const flr_solve_opts* o, double* beta_out,
                         flr_result* res) {
   flr_status v = validate_lambdas(l1, l2, tol);
@@ -511,6 +556,69 @@ flr_status flr_solve(flr_problem h, double l1, double l2, double tol, double* be
     if (iterations_out) *iterations_out = r.mm_iters;
   }
   return st;
+}
+
+flr_status flr_solve_batch(const flr_problem* hs, int32_t count, const double* l1, const double* l2, double tol,
+                           const flr_solve_opts* opts, double* const* beta_out, flr_result* res) {
+  if (!hs || !l1 || !l2 || count < 1) return fail(FLR_ERR_INVALID_ARG, "flr_solve_batch: bad arguments");
+  for (int32_t i = 0; i < count; ++i) {
+    if (!hs[i]) return fail(FLR_ERR_INVALID_ARG, "flr_solve_batch: NULL problem");
+    for (int32_t k = 0; k < i; ++k)
+      if (hs[k] == hs[i]) return fail(FLR_ERR_INVALID_ARG, "flr_solve_batch: a problem appears twice");
+    if (hs[i]->ctx->device != hs[0]->ctx->device)
+      return fail(FLR_ERR_INVALID_ARG, "flr_solve_batch: problems on different devices");
+    flr_status v = validate_lambdas(l1[i], l2[i], tol);
+    if (v != FLR_OK) return v;
+  }
+  std::vector<std::unique_lock<std::mutex>> locks;
+  for (int32_t i = 0; i < count; ++i) {
+    locks.emplace_back(hs[i]->busy, std::try_to_lock);
+    if (!locks.back().owns_lock()) return fail(FLR_ERR_BUSY, "flr_solve_batch: a problem handle is in use");
+  }
+  if (hipSetDevice(hs[0]->ctx->device) != hipSuccess) return fail(FLR_ERR_DEVICE, "hipSetDevice failed");
+  std::vector<SolveRun> runs((size_t)count);
+  for (int32_t i = 0; i < count; ++i) {
+    flr_status st = solve_begin(hs[i], l1[i], l2[i], tol, opts, runs[(size_t)i]);
+    if (st != FLR_OK) {
+      for (int32_t k = 0; k < i; ++k) (void)hipStreamSynchronize(hs[k]->stream);
+      return st;
+    }
+  }
+  // one host thread keeps every solve's rotation in flight on its own stream
+  int32_t left = count;
+  while (left > 0) {
+    bool any = false;
+    left = 0;
+    for (auto& run : runs) {
+      if (run.done) continue;
+      bool moved = false;
+      flr_status st = solve_advance(run, false, &moved);
+      if (st != FLR_OK) {
+        for (auto& r2 : runs) (void)hipStreamSynchronize(r2.h->stream);
+        return st;
+      }
+      any = any || moved;
+      if (!run.done) ++left;
+    }
+    if (!any && left > 0) {  // nothing retired this pass: wait for the first unfinished solve's older launch
+      for (auto& run : runs) {
+        if (run.done) continue;
+        bool moved = false;
+        flr_status st = solve_advance(run, true, &moved);
+        if (st != FLR_OK) {
+          for (auto& r2 : runs) (void)hipStreamSynchronize(r2.h->stream);
+          return st;
+        }
+        break;
+      }
+    }
+  }
+  flr_status first = FLR_OK;
+  for (int32_t i = 0; i < count; ++i) {
+    flr_status st = solve_end(runs[(size_t)i], beta_out ? beta_out[i] : nullptr, res ? &res[i] : nullptr);
+    if (st != FLR_OK && first == FLR_OK) first = st;
+  }
+  return first;
 }
 
 flr_status flr_profile_kernels(flr_problem h, int32_t reps, double* avg_us) {

@@ -132,3 +132,35 @@ def test_poll_not_ready_and_unknown_ticket(flr, ctx):
     flr.flr_server_destroy(srv)
     for p in probs:
         p.close()
+
+
+def test_ragged_batch_equals_solo_solves(flr, ctx):
+    # problems of uneven p and different graphs in one call: each result is the solo solve's
+    insts = [
+        flrgen.small_instance(120, 2000, "chain", dtype=flrgen.F32, seed=61, lam1=0.3, lam2=0.6),
+        flrgen.small_instance(80, 400, "lattice", dtype=flrgen.F64, seed=62, lam1=0.2, lam2=0.4, q=20),
+        flrgen.small_instance(40, 60, "allpairs", dtype=flrgen.F64, seed=63, lam1=0.5, lam2=0.05),
+        flrgen.small_instance(60, 300, "chain", dtype=flrgen.BF16, seed=64, lam1=0.1, lam2=0.2),
+    ]
+    l1 = [i.lam1 for i in insts]
+    l2 = [i.lam2 for i in insts]
+    solo = []
+    for inst, a, b in zip(insts, l1, l2):
+        p = flr.Problem.from_instance(ctx, inst)
+        solo.append(p.solve(a, b, tol=1e-7))
+        p.close()
+    probs = [flr.Problem.from_instance(ctx, i) for i in insts]
+    betas = [np.zeros(i.p) for i in insts]
+    st, res = flr.flr_solve_batch(probs, l1, l2, 1e-7, betas=betas)
+    for k, (s1, r, bta) in enumerate(zip(solo, res, betas)):
+        print("  %-28s solo mm=%d cg=%d | batch mm=%d cg=%d" % (insts[k].name, s1.mm_iters, s1.cg_iters, r.mm_iters,
+                                                                 r.cg_iters), flush=True)
+        assert r.status == s1.status
+        assert r.mm_iters == s1.mm_iters and r.cg_iters == s1.cg_iters
+        assert np.array_equal(bta, s1.beta)
+        assert r.objective == s1.objective
+    with pytest.raises(flr.FlrError) as ei:  # the same handle twice
+        flr.flr_solve_batch([probs[0], probs[0]], [0.1, 0.2], [0.1, 0.2], 1e-6)
+    assert ei.value.status == flr.FLR_ERR_INVALID_ARG
+    for p in probs:
+        p.close()
