@@ -17,9 +17,10 @@
 // each step reads the current element's right-hand side b_j from its lane and
 // subtracts b_j times (multiplier / L_jj) from the ring with one fma per
 // register; the solution b_j / L_jj of a chunk of 64 elements is formed once
-// the chunk is done.  The other three waves of the workgroup stage the scaled
-// multipliers of the coming steps into LDS, permuted to the ring's slot order,
-// with their loads issued a sub-chunk ahead.
+// the chunk is done.  The factorization also writes every step's multipliers
+// in the ring's slot order (RotF, RotB: p x 64 NR), so the other three waves
+// of the workgroup stage the coming steps' multipliers into LDS as a
+// contiguous copy, with their loads issued a sub-chunk ahead.
 #pragma once
 #include "flr_device.h"
 
@@ -68,7 +69,8 @@ __device__ inline void band_assemble(const double* __restrict__ d, const int32_t
 // later.  256 threads; returns false in every thread when a pivot is not
 // positive and finite.
 __device__ inline bool band_factor(double* __restrict__ Lb, double* __restrict__ LbT, double* __restrict__ invd,
-                                   int64_t p, int W, double* __restrict__ lds) {
+                                   int64_t p, int W, double* __restrict__ lds, double* __restrict__ RotF,
+                                   double* __restrict__ RotB) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int tx = tid & 15, ty = tid >> 4;
   constexpr int E = 4;  // extra ring slots = load-ahead distance in steps
@@ -163,6 +165,19 @@ __device__ inline bool band_factor(double* __restrict__ Lb, double* __restrict__
       if (idx - i * W) LbT[idx] *= invd[i];
     }
     __syncthreads();
+    // the multipliers of every sweep step in ring-slot order (see band_sweep_t):
+    // Rot[t*RS + s] multiplies the element in slot s at step t (k = distance)
+    const int RS = 64 * band_nr(W);
+    const int64_t rot = p * (int64_t)RS;
+    for (int64_t idx = tid; idx < rot; idx += nt) {
+      const int64_t t = idx / RS;
+      int k = (int)(idx - t * RS) - (int)(t % RS);
+      if (k < 0) k += RS;
+      const bool in = k >= 1 && k < W;
+      RotF[idx] = in ? Lb[t * W + k] : 0.0;
+      RotB[idx] = in ? LbT[(p - 1 - t) * W + k] : 0.0;
+    }
+    __syncthreads();
   }
   return ok;
 }
@@ -222,40 +237,35 @@ __device__ __forceinline__ void band_steps_sw(int r0, double (&reg)[NR], double&
 
 // One triangular sweep: virtual step t handles element e(t) = t (forward,
 // L y = b with the columns of L) or p - 1 - t (backward, L^T z = b with the
-// rows of L); the multipliers of step t are Mult[e(t)*W + k] for the element
-// k steps further along.  Whole workgroup of 256 threads; stage: kBandLds
+// rows of L); Rot[t*64NR + s] is the multiplier (already divided by L_jj) of
+// the element in ring slot s at step t, zero where that element is not within
+// the band.  Whole workgroup of 256 threads; stage: kBandLds
 // doubles of LDS.  Ends with a barrier.
 template <int NR, int SC>
-__device__ __forceinline__ void band_sweep_t(const double* __restrict__ b, double* __restrict__ out, const double* __restrict__ Mult,
+__device__ __forceinline__ void band_sweep_t(const double* __restrict__ b, double* __restrict__ out, const double* __restrict__ Rot,
                              const double* __restrict__ invd, int64_t p, int W, bool fwd, double* __restrict__ stage) {
   constexpr int RS = 64 * NR;
   constexpr int BUF = SC * NR * 64;
   static_assert(2 * BUF <= kBandLds, "stage buffers exceed the LDS budget");
   static_assert(64 % SC == 0, "sub-chunks must tile a chunk");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int bw = W - 1;
   const int64_t nsub = (p + SC - 1) / SC;
   auto elem = [&](int64_t t) { return fwd ? t : p - 1 - t; };
-  // Waves 1..3 stage sub-chunk s: thread i of the 192 takes elements i,
-  // i + 192, ... of the sub-chunk's SC x NR x 64 multipliers (step-major, then
-  // ring register, then lane, the order wave 0 reads them).  All PER loads of
-  // a thread are issued before any is written to LDS, one sub-chunk early
-  // (into pend), so their latency hides behind wave 0's steps.
+  // Waves 1..3 stage sub-chunk s: its multipliers are stored in ring order
+  // (Rot, written with the factor), so staging is a contiguous copy of
+  // SC x 64 NR doubles.  All PER loads of a thread are issued before any is
+  // written to LDS, one sub-chunk early (into pend), so their latency hides
+  // behind wave 0's steps.
   constexpr int NL = kWG - 64;
   constexpr int PER = (BUF + NL - 1) / NL;
   double pend[PER];
+  const int64_t rot_end = p * (int64_t)RS;
   auto stage_load = [&](int64_t s) {
-    const int64_t t0 = s * SC;
-    const int r0 = (int)((t0 / 64) % NR);
-    const int lc0 = (int)(t0 % 64);
+    const int64_t base = s * SC * (int64_t)RS;
 #pragma unroll
     for (int m = 0; m < PER; ++m) {
       const int i = tid - 64 + NL * m;
-      const int l = i / (NR * 64), rem = i - l * (NR * 64), r = rem >> 6, ln = rem & 63;
-      const int64_t t = t0 + l;
-      int k = ((r - r0 + NR) % NR) * 64 + ln - (lc0 + l);
-      if (k < 0) k += RS;
-      pend[m] = (i < BUF && t < p && k >= 1 && k <= bw) ? Mult[elem(t) * W + k] : 0.0;
+      pend[m] = (i < BUF && base + i < rot_end) ? Rot[base + i] : 0.0;
     }
   };
   auto stage_store = [&](double* buf) {
@@ -323,24 +333,24 @@ __device__ __forceinline__ void band_sweep_t(const double* __restrict__ b, doubl
 }
 
 template <int NR>
-__device__ __forceinline__ void band_solve_nr(const double* r, double* tmp, double* z, const double* Lb, const double* LbT,
-                                     const double* invd, int64_t p, int W, double* lds) {
+__device__ __forceinline__ void band_solve_nr(const double* r, double* tmp, double* z, const double* RotF,
+                                              const double* RotB, const double* invd, int64_t p, int W, double* lds) {
   constexpr int SC = (2 * 32 * NR * 64 <= kBandLds) ? 32 : (2 * 16 * NR * 64 <= kBandLds) ? 16
                      : (2 * 8 * NR * 64 <= kBandLds) ? 8 : 4;
-  band_sweep_t<NR, SC>(r, tmp, Lb, invd, p, W, true, lds);
-  band_sweep_t<NR, SC>(tmp, z, LbT, invd, p, W, false, lds);
+  band_sweep_t<NR, SC>(r, tmp, RotF, invd, p, W, true, lds);
+  band_sweep_t<NR, SC>(tmp, z, RotB, invd, p, W, false, lds);
 }
 
 // z = M^-1 r = L^-T L^-1 r through tmp (p doubles).  Whole workgroup of 256
 // threads; W <= kBandMaxW (checked on the host).  Ends with a barrier.
-__device__ __forceinline__ void band_solve(const double* r, double* tmp, double* z, const double* Lb, const double* LbT,
-                                  const double* invd, int64_t p, int W, double* lds) {
+__device__ __forceinline__ void band_solve(const double* r, double* tmp, double* z, const double* RotF,
+                                           const double* RotB, const double* invd, int64_t p, int W, double* lds) {
   switch (band_nr(W)) {
-    case 2: band_solve_nr<2>(r, tmp, z, Lb, LbT, invd, p, W, lds); break;
-    case 3: band_solve_nr<3>(r, tmp, z, Lb, LbT, invd, p, W, lds); break;
-    case 5: band_solve_nr<5>(r, tmp, z, Lb, LbT, invd, p, W, lds); break;
-    case 8: band_solve_nr<8>(r, tmp, z, Lb, LbT, invd, p, W, lds); break;
-    default: band_solve_nr<17>(r, tmp, z, Lb, LbT, invd, p, W, lds); break;
+    case 2: band_solve_nr<2>(r, tmp, z, RotF, RotB, invd, p, W, lds); break;
+    case 3: band_solve_nr<3>(r, tmp, z, RotF, RotB, invd, p, W, lds); break;
+    case 5: band_solve_nr<5>(r, tmp, z, RotF, RotB, invd, p, W, lds); break;
+    case 8: band_solve_nr<8>(r, tmp, z, RotF, RotB, invd, p, W, lds); break;
+    default: band_solve_nr<17>(r, tmp, z, RotF, RotB, invd, p, W, lds); break;
   }
 }
 
