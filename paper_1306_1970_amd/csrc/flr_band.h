@@ -17,10 +17,11 @@
 // each step reads the current element's right-hand side b_j from its lane and
 // subtracts b_j times (multiplier / L_jj) from the ring with one fma per
 // register; the solution b_j / L_jj of a chunk of 64 elements is formed once
-// the chunk is done.  The factorization also writes every step's multipliers
-// in the ring's slot order (RotF, RotB: p x 64 NR), so the other three waves
-// of the workgroup stage the coming steps' multipliers into LDS as a
-// contiguous copy, with their loads issued a sub-chunk ahead.
+// the chunk is done.  The other three waves of the workgroup stage the
+// coming steps' multipliers into LDS in the ring's slot order, straight from
+// Lb / LbT: each staging thread owns fixed ring distances k and walks the
+// steps of a sub-chunk (one row of W multipliers per step, read coalesced
+// across threads), with its loads issued a sub-chunk ahead.
 #pragma once
 #include "flr_device.h"
 
@@ -69,8 +70,7 @@ __device__ inline void band_assemble(const double* __restrict__ d, const int32_t
 // later.  256 threads; returns false in every thread when a pivot is not
 // positive and finite.
 __device__ inline bool band_factor(double* __restrict__ Lb, double* __restrict__ LbT, double* __restrict__ invd,
-                                   int64_t p, int W, double* __restrict__ lds, double* __restrict__ RotF,
-                                   double* __restrict__ RotB) {
+                                   int64_t p, int W, double* __restrict__ lds) {
   const int tid = threadIdx.x, nt = blockDim.x;
   const int tx = tid & 15, ty = tid >> 4;
   constexpr int E = 4;  // extra ring slots = load-ahead distance in steps
@@ -165,19 +165,6 @@ __device__ inline bool band_factor(double* __restrict__ Lb, double* __restrict__
       if (idx - i * W) LbT[idx] *= invd[i];
     }
     __syncthreads();
-    // the multipliers of every sweep step in ring-slot order (see band_sweep_t):
-    // Rot[t*RS + s] multiplies the element in slot s at step t (k = distance)
-    const int RS = 64 * band_nr(W);
-    const int64_t rot = p * (int64_t)RS;
-    for (int64_t idx = tid; idx < rot; idx += nt) {
-      const int64_t t = idx / RS;
-      int k = (int)(idx - t * RS) - (int)(t % RS);
-      if (k < 0) k += RS;
-      const bool in = k >= 1 && k < W;
-      RotF[idx] = in ? Lb[t * W + k] : 0.0;
-      RotB[idx] = in ? LbT[(p - 1 - t) * W + k] : 0.0;
-    }
-    __syncthreads();
   }
   return ok;
 }
@@ -236,13 +223,13 @@ __device__ __forceinline__ void band_steps_sw(int r0, double (&reg)[NR], double&
 }
 
 // One triangular sweep: virtual step t handles element e(t) = t (forward,
-// L y = b with the columns of L) or p - 1 - t (backward, L^T z = b with the
-// rows of L); Rot[t*64NR + s] is the multiplier (already divided by L_jj) of
-// the element in ring slot s at step t, zero where that element is not within
-// the band.  Whole workgroup of 256 threads; stage: kBandLds
-// doubles of LDS.  Ends with a barrier.
+// L y = b with the columns of L, Mul = Lb) or p - 1 - t (backward, L^T z = b
+// with the rows of L, Mul = LbT); Mul[e(t)*W + k] (1 <= k < W) multiplies the
+// element k steps ahead, which sits in ring slot (t + k) mod 64 NR.  Whole
+// workgroup of 256 threads; stage: kBandLds doubles of LDS.  Ends with a
+// barrier.
 template <int NR, int SC>
-__device__ __forceinline__ void band_sweep_t(const double* __restrict__ b, double* __restrict__ out, const double* __restrict__ Rot,
+__device__ __forceinline__ void band_sweep_t(const double* __restrict__ b, double* __restrict__ out, const double* __restrict__ Mul,
                              const double* __restrict__ invd, int64_t p, int W, bool fwd, double* __restrict__ stage) {
   constexpr int RS = 64 * NR;
   constexpr int BUF = SC * NR * 64;
@@ -251,28 +238,46 @@ __device__ __forceinline__ void band_sweep_t(const double* __restrict__ b, doubl
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t nsub = (p + SC - 1) / SC;
   auto elem = [&](int64_t t) { return fwd ? t : p - 1 - t; };
-  // Waves 1..3 stage sub-chunk s: its multipliers are stored in ring order
-  // (Rot, written with the factor), so staging is a contiguous copy of
-  // SC x 64 NR doubles.  All PER loads of a thread are issued before any is
-  // written to LDS, one sub-chunk early (into pend), so their latency hides
-  // behind wave 0's steps.
+  // Waves 1..3 stage sub-chunk s: staging thread u owns the ring distances
+  // k = u + NL c (c < KC) and, for each of the SC steps, loads the multiplier
+  // at distance k (zero outside 1 <= k < W or past the end) and stores it into
+  // the LDS row of that step at slot (t + k) mod RS.  Every slot of a row is
+  // written, so stale values never survive.  All PER loads of a thread are
+  // issued before any is written to LDS, one sub-chunk early (into pend), so
+  // their latency hides behind wave 0's steps.
   constexpr int NL = kWG - 64;
-  constexpr int PER = (BUF + NL - 1) / NL;
+  constexpr int KC = (RS + NL - 1) / NL;
+  constexpr int PER = KC * SC;
+  const int u = tid - 64;
+  const int64_t rstep = fwd ? (int64_t)W : -(int64_t)W;
   double pend[PER];
-  const int64_t rot_end = p * (int64_t)RS;
   auto stage_load = [&](int64_t s) {
-    const int64_t base = s * SC * (int64_t)RS;
+    const int64_t t0 = s * SC;
+    const int64_t rem = p - t0;
+    const int lim = rem < SC ? (int)rem : SC;
+    const double* row = Mul + elem(t0) * (int64_t)W;
 #pragma unroll
-    for (int m = 0; m < PER; ++m) {
-      const int i = tid - 64 + NL * m;
-      pend[m] = (i < BUF && base + i < rot_end) ? Rot[base + i] : 0.0;
+    for (int c = 0; c < KC; ++c) {
+      const int k = u + NL * c;
+      const bool kin = k >= 1 && k < W;
+#pragma unroll
+      for (int l = 0; l < SC; ++l) pend[c * SC + l] = (kin && l < lim) ? row[l * rstep + k] : 0.0;
     }
   };
-  auto stage_store = [&](double* buf) {
+  auto stage_store = [&](double* buf, int64_t s) {
+    const int rr0 = (int)((s * SC) % RS);
 #pragma unroll
-    for (int m = 0; m < PER; ++m) {
-      const int i = tid - 64 + NL * m;
-      if (i < BUF) buf[i] = pend[m];
+    for (int c = 0; c < KC; ++c) {
+      const int k = u + NL * c;
+      if (k < RS) {
+        int slot = rr0 + k;
+        if (slot >= RS) slot -= RS;
+#pragma unroll
+        for (int l = 0; l < SC; ++l) {
+          buf[l * RS + slot] = pend[c * SC + l];
+          slot = slot + 1 == RS ? 0 : slot + 1;
+        }
+      }
     }
   };
   double reg[NR];
@@ -296,14 +301,14 @@ __device__ __forceinline__ void band_sweep_t(const double* __restrict__ b, doubl
     load_chunk(0, idv_nx, nb_nx);
   } else {
     stage_load(0);
-    stage_store(stage);
+    stage_store(stage, 0);
     if (nsub > 1) stage_load(1);
   }
   __syncthreads();
   for (int64_t s = 0; s < nsub; ++s) {
     double* cur = stage + (s & 1) * BUF;
     if (wave != 0) {
-      if (s + 1 < nsub) stage_store(stage + ((s + 1) & 1) * BUF);
+      if (s + 1 < nsub) stage_store(stage + ((s + 1) & 1) * BUF, s + 1);
       if (s + 2 < nsub) stage_load(s + 2);
     } else {
       const int64_t t0 = s * SC;
@@ -333,24 +338,24 @@ __device__ __forceinline__ void band_sweep_t(const double* __restrict__ b, doubl
 }
 
 template <int NR>
-__device__ __forceinline__ void band_solve_nr(const double* r, double* tmp, double* z, const double* RotF,
-                                              const double* RotB, const double* invd, int64_t p, int W, double* lds) {
+__device__ __forceinline__ void band_solve_nr(const double* r, double* tmp, double* z, const double* Lb,
+                                              const double* LbT, const double* invd, int64_t p, int W, double* lds) {
   constexpr int SC = (2 * 32 * NR * 64 <= kBandLds) ? 32 : (2 * 16 * NR * 64 <= kBandLds) ? 16
                      : (2 * 8 * NR * 64 <= kBandLds) ? 8 : 4;
-  band_sweep_t<NR, SC>(r, tmp, RotF, invd, p, W, true, lds);
-  band_sweep_t<NR, SC>(tmp, z, RotB, invd, p, W, false, lds);
+  band_sweep_t<NR, SC>(r, tmp, Lb, invd, p, W, true, lds);
+  band_sweep_t<NR, SC>(tmp, z, LbT, invd, p, W, false, lds);
 }
 
 // z = M^-1 r = L^-T L^-1 r through tmp (p doubles).  Whole workgroup of 256
 // threads; W <= kBandMaxW (checked on the host).  Ends with a barrier.
-__device__ __forceinline__ void band_solve(const double* r, double* tmp, double* z, const double* RotF,
-                                           const double* RotB, const double* invd, int64_t p, int W, double* lds) {
+__device__ __forceinline__ void band_solve(const double* r, double* tmp, double* z, const double* Lb,
+                                           const double* LbT, const double* invd, int64_t p, int W, double* lds) {
   switch (band_nr(W)) {
-    case 2: band_solve_nr<2>(r, tmp, z, RotF, RotB, invd, p, W, lds); break;
-    case 3: band_solve_nr<3>(r, tmp, z, RotF, RotB, invd, p, W, lds); break;
-    case 5: band_solve_nr<5>(r, tmp, z, RotF, RotB, invd, p, W, lds); break;
-    case 8: band_solve_nr<8>(r, tmp, z, RotF, RotB, invd, p, W, lds); break;
-    default: band_solve_nr<17>(r, tmp, z, RotF, RotB, invd, p, W, lds); break;
+    case 2: band_solve_nr<2>(r, tmp, z, Lb, LbT, invd, p, W, lds); break;
+    case 3: band_solve_nr<3>(r, tmp, z, Lb, LbT, invd, p, W, lds); break;
+    case 5: band_solve_nr<5>(r, tmp, z, Lb, LbT, invd, p, W, lds); break;
+    case 8: band_solve_nr<8>(r, tmp, z, Lb, LbT, invd, p, W, lds); break;
+    default: band_solve_nr<17>(r, tmp, z, Lb, LbT, invd, p, W, lds); break;
   }
 }
 

@@ -483,8 +483,6 @@ flr_status flr_create(flr_ctx ctx, const void* X, flr_dtype x_dtype, int64_t n, 
       CK(dalloc(h, &B.Lb, (size_t)p * (size_t)W));
       CK(dalloc(h, &B.LbT, (size_t)p * (size_t)W));
       CK(dalloc(h, &B.invdb, (size_t)D.p_pad));
-      CK(dalloc(h, &B.RotF, (size_t)p * (size_t)(64 * band_nr((int)W))));
-      CK(dalloc(h, &B.RotB, (size_t)p * (size_t)(64 * band_nr((int)W))));
       CK(dalloc(h, &B.btmp, (size_t)D.p_pad));
       h->band_w = (int)W;
     }

@@ -73,8 +73,6 @@ struct GridDev {
   const int32_t* map;  // GEMM slot -> column (active columns only, in slot order)
   double* Lb;          // banded factor by columns, B x p x W (banded mode)
   double* LbT;         // the same by rows
-  double* RotF;        // sweep multipliers in ring order, B x p x 64 NR
-  double* RotB;
 };
 
 constexpr int kE = 8;              // consecutive elements per thread in a chunk
@@ -200,9 +198,6 @@ __global__ __launch_bounds__(kWG) void k_col(GridDev G) {
   const int W = prm.band;
   double* Lbb = BAND ? G.Lb + (int64_t)b * G.p * W : nullptr;
   double* LbTb = BAND ? G.LbT + (int64_t)b * G.p * W : nullptr;
-  const int64_t RSz = BAND ? (int64_t)64 * band_nr(W) : 0;
-  double* RotFb = BAND ? G.RotF + (int64_t)b * G.p * RSz : nullptr;
-  double* RotBb = BAND ? G.RotB + (int64_t)b * G.p * RSz : nullptr;
   const double l1 = G.lam1[b], l2 = G.lam2[b];
   const int64_t p = G.p, P = G.p_pad, off = (int64_t)b * P;
   double* x = G.x + off;
@@ -310,7 +305,7 @@ __global__ __launch_bounds__(kWG) void k_col(GridDev G) {
     __syncthreads();
     if (use_band) {
       band_assemble(d, G.rowptr, G.col, w, l2, p, W, Lbb);
-      if (!band_factor(Lbb, LbTb, G.invD + off, p, W, bl, RotFb, RotBb)) {
+      if (!band_factor(Lbb, LbTb, G.invD + off, p, W, bl)) {
         s.status = ST_NUMERICAL;
         s.phase = PH_DONE;
         for (int64_t j = tid; j < P; j += kWG) O[j] = 0.0;
@@ -326,7 +321,7 @@ __global__ __launch_bounds__(kWG) void k_col(GridDev G) {
   }
   // z = M^-1 r (one call site for both branches)
   if (use_band)
-    band_solve(r, G.g + off, z, RotFb, RotBb, G.invD + off, p, W, bl);
+    band_solve(r, G.g + off, z, Lbb, LbTb, G.invD + off, p, W, bl);
   else
     col_tri_solve(r, G.L + off, G.invD + off, G.g + off, z, p, lds, sh2);
   double rzp = 0.0, rrp = 0.0;
@@ -534,12 +529,10 @@ static flr_status grid_prepare(flr_problem h, int B, bool band) {
     if (band && !h->grid->G.Lb) {
       GridWork* gw = h->grid;
       const size_t nb = (size_t)gw->cap * (size_t)D.p * (size_t)h->band_w;
-      const size_t nr = (size_t)gw->cap * (size_t)D.p * (size_t)(64 * band_nr(h->band_w));
-      for (double** ptr : {&gw->G.Lb, &gw->G.LbT, &gw->G.RotF, &gw->G.RotB}) {
-        const size_t cnt = (ptr == &gw->G.Lb || ptr == &gw->G.LbT) ? nb : nr;
-        GCK(hipMalloc(reinterpret_cast<void**>(ptr), cnt * sizeof(double)));
+      for (double** ptr : {&gw->G.Lb, &gw->G.LbT}) {
+        GCK(hipMalloc(reinterpret_cast<void**>(ptr), nb * sizeof(double)));
         gw->allocs.push_back(*ptr);
-        GCK(hipMemsetAsync(*ptr, 0, cnt * sizeof(double), h->stream));
+        GCK(hipMemsetAsync(*ptr, 0, nb * sizeof(double), h->stream));
       }
     }
     return FLR_OK;
@@ -576,8 +569,6 @@ static flr_status grid_prepare(flr_problem h, int B, bool band) {
   if (band) {
     GCK(al(&G.Lb, (size_t)B * (size_t)D.p * (size_t)h->band_w));
     GCK(al(&G.LbT, (size_t)B * (size_t)D.p * (size_t)h->band_w));
-    GCK(al(&G.RotF, (size_t)B * (size_t)D.p * (size_t)(64 * band_nr(h->band_w))));
-    GCK(al(&G.RotB, (size_t)B * (size_t)D.p * (size_t)(64 * band_nr(h->band_w))));
   }
   GCK(al(&gw->d_lam, 2 * (size_t)B));
   double* tmp = nullptr;

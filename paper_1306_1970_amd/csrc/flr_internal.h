@@ -97,8 +97,6 @@ struct Bufs {
   double* Lb;       // banded Cholesky factor of M by columns, p x W (banded mode only)
   double* LbT;      // the same by rows
   double* invdb;    // 1 / L_jj
-  double* RotF;     // forward-sweep multipliers in ring order, p x 64 NR
-  double* RotB;     // backward-sweep multipliers in ring order
   double* btmp;     // intermediate of the two triangular sweeps
   unsigned* counter;// blocks of the current C launch that have finished
   State* st;        // 2

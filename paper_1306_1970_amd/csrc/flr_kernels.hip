@@ -849,7 +849,7 @@ __global__ __launch_bounds__(kWG) void k_band(Dims D, Bufs B, const State* __res
   State o = s;
   if (mm) {
     band_assemble(B.d, B.rowptr, B.col, B.w, prm.lam2, D.p, W, B.Lb);
-    if (!band_factor(B.Lb, B.LbT, B.invdb, D.p, W, lds, B.RotF, B.RotB)) {
+    if (!band_factor(B.Lb, B.LbT, B.invdb, D.p, W, lds)) {
       if (tid == 0) {
         o.phase = PH_DONE;
         o.status = ST_NUMERICAL;
@@ -859,7 +859,7 @@ __global__ __launch_bounds__(kWG) void k_band(Dims D, Bufs B, const State* __res
     }
     __syncthreads();
   }
-  band_solve(B.r, B.btmp, B.yv, B.RotF, B.RotB, B.invdb, D.p, W, lds);
+  band_solve(B.r, B.btmp, B.yv, B.Lb, B.LbT, B.invdb, D.p, W, lds);
   double rzp = 0.0, rrp = 0.0;
   for (int64_t j = tid; j < D.p; j += kWG) {
     const double rj = B.r[j];
