@@ -74,8 +74,9 @@ __device__ inline bool band_factor(double* __restrict__ Lb, double* __restrict__
   const int tid = threadIdx.x, nt = blockDim.x;
   const int tx = tid & 15, ty = tid >> 4;
   constexpr int E = 4;  // extra ring slots = load-ahead distance in steps
+  constexpr int kRingB = 7;  // 16-wide blocks of offsets 1 .. W - 1 in the ring (W <= 113)
   const int R = W + E;
-  const bool ring = (int64_t)R * W <= kBandLds && W <= nt;
+  const bool ring = (int64_t)R * W <= kBandLds && W <= nt && W - 1 <= 16 * kRingB;
   bool ok = true;
   if (ring) {
     const int64_t ncol = p < (int64_t)(W + E - 1) ? p : (int64_t)(W + E - 1);
@@ -87,13 +88,14 @@ __device__ inline bool band_factor(double* __restrict__ Lb, double* __restrict__
       nxt[u] = (tid < W && c < p) ? Lb[c * W + tid] : 0.0;
     }
     __syncthreads();
+    int jr = 0;  // j mod R, kept incrementally (ring positions stay 32-bit)
     for (int64_t jb = 0; jb < p && ok; jb += E) {
 #pragma unroll
       for (int u = 0; u < E; ++u) {
         const int64_t j = jb + u;
         if (j >= p) break;
         const int dmax = (int)((p - 1 - j) < (int64_t)(W - 1) ? (p - 1 - j) : (int64_t)(W - 1));
-        const double* cj = lds + (j % R) * W;
+        const double* cj = lds + jr * W;
         const double piv = cj[0];
         if (!(piv > 0.0) || !isfinite(piv)) {
           ok = false;
@@ -106,13 +108,41 @@ __device__ inline bool band_factor(double* __restrict__ Lb, double* __restrict__
           LbT[(j + d) * W + d] = v;
         }
         if (tid == 0) invd[j] = inv;
-        for (int d1 = 1 + ty; d1 <= dmax; d1 += 16) {
-          const double s1 = cj[d1] * inv;
-          double* tgt = lds + ((j + d1) % R) * W - d1;
-          for (int d2 = d1 + tx; d2 <= dmax; d2 += 16) tgt[d2] = fma(-s1, cj[d2] * inv, tgt[d2]);
+        // rank-1 update of columns j+1 .. j+dmax: thread (tx, ty) owns the
+        // pairs d1 = 1 + ty + 16 a (column), d2 = 1 + tx + 16 c (row), d1 <= d2;
+        // all its targets are read before any is written (they are distinct)
+        double sr[kRingB], scl[kRingB], tv[kRingB][kRingB];
+#pragma unroll
+        for (int a = 0; a < kRingB; ++a) {
+          const int d = 1 + 16 * a;
+          sr[a] = d + tx <= dmax ? cj[d + tx] * inv : 0.0;
+          scl[a] = d + ty <= dmax ? cj[d + ty] * inv : 0.0;
         }
-        const int64_t cin = j + W + E - 1;  // enters the ring now; first updated at step j + E
-        if (tid < W && cin < p) lds[(cin % R) * W + tid] = nxt[u];
+#pragma unroll
+        for (int a = 0; a < kRingB; ++a) {
+          const int d1 = 1 + ty + 16 * a;
+          const int slot = jr + d1 < R ? jr + d1 : jr + d1 - R;
+          const double* tgt = lds + slot * W - d1;
+#pragma unroll
+          for (int c = a; c < kRingB; ++c) {
+            const int d2 = 1 + tx + 16 * c;
+            if (d1 <= d2 && d2 <= dmax) tv[a][c] = tgt[d2];
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < kRingB; ++a) {
+          const int d1 = 1 + ty + 16 * a;
+          const int slot = jr + d1 < R ? jr + d1 : jr + d1 - R;
+          double* tgt = lds + slot * W - d1;
+#pragma unroll
+          for (int c = a; c < kRingB; ++c) {
+            const int d2 = 1 + tx + 16 * c;
+            if (d1 <= d2 && d2 <= dmax) tgt[d2] = fma(-scl[a], sr[c], tv[a][c]);
+          }
+        }
+        const int64_t cin = j + W + E - 1;  // enters the ring now (in slot (j - 1) mod R); first updated at step j + E
+        if (tid < W && cin < p) lds[(jr == 0 ? R - 1 : jr - 1) * W + tid] = nxt[u];
+        jr = jr + 1 == R ? 0 : jr + 1;
         const int64_t cnx = cin + E;
         nxt[u] = (tid < W && cnx < p) ? Lb[cnx * W + tid] : 0.0;
         lds_barrier();  // the loads of nxt stay in flight for E steps

@@ -183,8 +183,11 @@ __device__ inline double col_apply_m(const GridDev& G, int b, int64_t j, const d
 // are indexed by the column's slot in the active list; everything else by the
 // column itself.  BAND: columns with lambda1 > 0 apply M^-1 through its banded
 // Cholesky factor (graphs of bandwidth >= 2), the others the tridiagonal part.
+// hold: a column that has reached its MM boundary (PH_END) waits in this
+// launch; its operand O = x is unchanged, so the boundary it runs later sees
+// the same products U = X x, V = X^T X x.
 template <bool BAND>
-__global__ __launch_bounds__(kWG) void k_col(GridDev G) {
+__global__ __launch_bounds__(kWG) void k_col(GridDev G, int hold) {
   const int slot = blockIdx.x, tid = threadIdx.x;
   const int b = G.map[slot];
   __shared__ double lds[24];
@@ -192,7 +195,7 @@ __global__ __launch_bounds__(kWG) void k_col(GridDev G) {
   __shared__ double sh4[4 * kWG];
   __shared__ double bl[BAND ? kBandLds : 1];
   ColState s = G.st[b];
-  if (s.phase == PH_DONE) return;
+  if (s.phase == PH_DONE || (hold && s.phase == PH_END)) return;
   const GridParams prm = *G.prm;
   const bool use_band = BAND && !s.jacobi;
   const int W = prm.band;
@@ -663,9 +666,20 @@ static flr_status grid_run(flr_problem h, const double* l1, const double* l2, in
   GCK(hipGetLastError());
   const double one = 1.0, zero = 0.0;
   const int check_every = 8;
-  // every column needs at most max_iter * (max_cg + 2) + 1 steps; the host
-  // sees a finished batch up to two polling periods later
-  const int64_t max_steps = (int64_t)P.max_iter * ((int64_t)P.max_cg + 2) + 4 + 3 * check_every;
+  // Banded columns gather their MM boundaries into every hold_period-th
+  // launch while at least kHoldMinCols columns run: a boundary factors the
+  // band in one workgroup (tens of ms at bandwidth 100), and columns reach
+  // their boundaries at different steps, so without this almost every launch
+  // would wait for some column's factorization.  A held column only idles;
+  // its arithmetic is unchanged.  FLR_GRID_HOLD overrides the period (0 or 1:
+  // no holding).
+  constexpr int kHoldMinCols = 8;
+  int hold_period = band ? 16 : 1;
+  if (const char* hv = std::getenv("FLR_GRID_HOLD")) hold_period = std::max(1, std::atoi(hv));
+  // every column needs at most max_iter * (max_cg + 2 + hold_period) + 1
+  // steps; the host sees a finished batch up to two polling periods later
+  const int64_t max_steps =
+      (int64_t)P.max_iter * ((int64_t)P.max_cg + 2 + hold_period) + 4 + 3 * check_every;
   // active columns in slot order; compacted when enough of them have finished
   std::vector<int32_t> act((size_t)B);
   for (int i = 0; i < B; ++i) act[(size_t)i] = i;
@@ -697,10 +711,11 @@ static flr_status grid_run(flr_problem h, const double* l1, const double* l2, in
                       (rocblas_int)D.n, &one, h->X64, (rocblas_int)D.ldx, G.U, (rocblas_int)D.n, &zero, G.V,
                       (rocblas_int)D.p_pad) != rocblas_status_success)
       return gfail(FLR_ERR_DEVICE, "rocblas_dgemm (X^T U) failed");
+    const int hold = hold_period > 1 && nact >= kHoldMinCols && step % hold_period != 0 ? 1 : 0;
     if (P.band)
-      hipLaunchKernelGGL(k_col<true>, dim3((unsigned)nact), dim3(kWG), 0, h->stream, G);
+      hipLaunchKernelGGL(k_col<true>, dim3((unsigned)nact), dim3(kWG), 0, h->stream, G, hold);
     else
-      hipLaunchKernelGGL(k_col<false>, dim3((unsigned)nact), dim3(kWG), 0, h->stream, G);
+      hipLaunchKernelGGL(k_col<false>, dim3((unsigned)nact), dim3(kWG), 0, h->stream, G, hold);
     GCK(hipGetLastError());
     ++step;
     if (step % check_every == 0) {

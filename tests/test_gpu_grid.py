@@ -155,3 +155,31 @@ def test_grid_lattice_banded(flr, ctx):
         assert res[b]["mm_iters"] == ref.mm_iters
         assert err <= 1e-8
         assert abs(res[b]["cg_iters"] - ref.cg_iters) <= max(5, ref.cg_iters // 50)
+
+
+def test_grid_lattice_held_boundaries(flr, ctx, monkeypatch):
+    # nine banded columns: while at least eight run, a column that reaches its MM boundary waits for the
+    # next shared boundary launch (every 16th); the held schedule must give every column the oracle's
+    # solution and the unheld schedule's
+    inst = flrgen.small_instance(80, 144, "lattice", dtype=flrgen.F32, seed=36)
+    l1, l2 = flrgen.grid_lambdas(np.array([0.1, 0.6, 2.0]))
+    prob = flr.Problem.from_instance(ctx, inst)
+    st, beta, res = prob.solve_grid(l1, l2, tol=1e-7, inner_tol=INNER)
+    monkeypatch.setenv("FLR_GRID_HOLD", "1")
+    st1, beta1, res1 = prob.solve_grid(l1, l2, tol=1e-7, inner_tol=INNER)
+    prob.close()
+    assert st == flr.FLR_OK and st1 == flr.FLR_OK
+    P = oracle.Problem.from_instance(inst)
+    for b in range(l1.size):
+        ref = oracle.solve(P, l1[b], l2[b], tol=1e-7, inner_tol=INNER, method=oracle.ALG2)
+        scale = np.max(np.abs(ref.beta))
+        err = np.max(np.abs(beta[b] - ref.beta)) / scale
+        err1 = np.max(np.abs(beta[b] - beta1[b])) / scale
+        print("  col %d held mm=%d cg=%d | unheld mm=%d cg=%d | oracle mm=%d err=%.2e vs unheld %.2e" % (
+            b, res[b]["mm_iters"], res[b]["cg_iters"], res1[b]["mm_iters"], res1[b]["cg_iters"], ref.mm_iters,
+            err, err1), flush=True)
+        assert res[b]["mm_iters"] == ref.mm_iters == res1[b]["mm_iters"]
+        # the products may come from different GEMM kernels (the number of active columns differs
+        # between the schedules), so the two agree to rounding, not bit for bit
+        assert abs(res[b]["cg_iters"] - res1[b]["cg_iters"]) <= 2
+        assert err <= 1e-8 and err1 <= 1e-10
