@@ -443,6 +443,17 @@ __global__ __launch_bounds__(kWG) void k_transpose64(const XT* __restrict__ X, d
   }
 }
 
+// U = sum of the split-K partial products, in slice order (fixed, so the
+// result does not depend on timing).
+__global__ __launch_bounds__(kWG) void k_sum_parts(const double* __restrict__ parts, double* __restrict__ out,
+                                                   int64_t cnt, int nparts) {
+  const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+  if (i >= cnt) return;
+  double acc = parts[i];
+  for (int q = 1; q < nparts; ++q) acc += parts[(int64_t)q * cnt + i];
+  out[i] = acc;
+}
+
 }  // namespace flr
 
 using namespace flr;
@@ -458,11 +469,34 @@ struct GridWork {
   ColState* h_st = nullptr;  // pinned, cap
   hipEvent_t ev = nullptr;
   double* O2 = nullptr;       // second operand buffer for compaction
+  int splitk = 1;             // K slices of U = X O
+  double* Upart = nullptr;    // splitk x n x cap partial products
   int32_t* d_map = nullptr;   // cap
   int32_t* d_from = nullptr;  // cap
 };
 
 namespace flr {
+// U = X O (column-major n x nact) from the column-major copy of X, split
+// over K into gw->splitk slices when that fills the chip better.
+static rocblas_status grid_xo(flr_problem h, GridWork* gw, const double* O, double* U, int nact) {
+  const Dims& D = h->D;
+  const double one = 1.0, zero = 0.0;
+  const int sk = gw->splitk;
+  if (sk <= 1)
+    return rocblas_dgemm(gw->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)D.n, nact,
+                         (rocblas_int)D.p_pad, &one, h->X64c, (rocblas_int)D.n, O, (rocblas_int)D.p_pad, &zero, U,
+                         (rocblas_int)D.n);
+  const int64_t kc = D.p_pad / sk, cnt = D.n * (int64_t)nact;
+  const rocblas_status st = rocblas_dgemm_strided_batched(
+      gw->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)D.n, nact, (rocblas_int)kc, &one,
+      h->X64c, (rocblas_int)D.n, (rocblas_stride)(kc * D.n), O, (rocblas_int)D.p_pad, (rocblas_stride)kc, &zero,
+      gw->Upart, (rocblas_int)D.n, (rocblas_stride)cnt, sk);
+  if (st != rocblas_status_success) return st;
+  hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((cnt + kWG - 1) / kWG)), dim3(kWG), 0, h->stream, gw->Upart, U,
+                     cnt, sk);
+  return hipGetLastError() == hipSuccess ? rocblas_status_success : rocblas_status_internal_error;
+}
+
 void grid_free(flr_problem h) {
   GridWork* gw = h->grid;
   if (!gw) return;
@@ -572,6 +606,16 @@ static flr_status grid_prepare(flr_problem h, int B, bool band) {
   if (band) {
     GCK(al(&G.Lb, (size_t)B * (size_t)D.p * (size_t)h->band_w));
     GCK(al(&G.LbT, (size_t)B * (size_t)D.p * (size_t)h->band_w));
+  }
+  {
+    // U = X O has an n x B output, a few dozen 128 x 128 tiles when n is a few
+    // thousand, each walking all of K = p_pad: split K so the product fills
+    // the chip (up to 512 tiles, slices of at least 1024)
+    const int64_t tiles = ((D.n + 127) / 128) * (((int64_t)B + 127) / 128);
+    int sk = 1;
+    while (sk < 8 && tiles * sk * 2 <= 512 && D.p_pad % (sk * 2 * 64) == 0 && D.p_pad / (sk * 2) >= 1024) sk *= 2;
+    gw->splitk = sk;
+    if (sk > 1) GCK(al(&gw->Upart, (size_t)sk * (size_t)D.n * (size_t)B));
   }
   GCK(al(&gw->d_lam, 2 * (size_t)B));
   double* tmp = nullptr;
@@ -702,10 +746,8 @@ static flr_status grid_run(flr_problem h, const double* l1, const double* l2, in
       std::fprintf(stderr, "flr grid: %lld batched steps, %d of %d columns active\n", (long long)step, nact, B);
     }
     // U = X O : column-major U (n x nact), X from its column-major copy
-    if (rocblas_dgemm(gw->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)D.n, nact,
-                      (rocblas_int)D.p_pad, &one, h->X64c, (rocblas_int)D.n, G.O, (rocblas_int)D.p_pad, &zero, G.U,
-                      (rocblas_int)D.n) != rocblas_status_success)
-      return gfail(FLR_ERR_DEVICE, "rocblas_dgemm (X O^T) failed");
+    if (grid_xo(h, gw, G.O, G.U, nact) != rocblas_status_success)
+      return gfail(FLR_ERR_DEVICE, "X O product (rocblas_dgemm) failed");
     // V = X^T U : p_pad x nact
     if (rocblas_dgemm(gw->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)D.p_pad, nact,
                       (rocblas_int)D.n, &one, h->X64, (rocblas_int)D.ldx, G.U, (rocblas_int)D.n, &zero, G.V,
@@ -810,11 +852,7 @@ extern "C" flr_status flr_profile_grid(flr_problem h, int32_t B, int32_t reps, d
   const double one = 1.0, zero = 0.0;
   hipEvent_t e[3];
   for (auto& ev : e) GCK(hipEventCreate(&ev));
-  auto gemm_u = [&]() {
-    return rocblas_dgemm(gw->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)D.n, B,
-                         (rocblas_int)D.p_pad, &one, h->X64c, (rocblas_int)D.n, gw->O2, (rocblas_int)D.p_pad, &zero,
-                         G.U, (rocblas_int)D.n);
-  };
+  auto gemm_u = [&]() { return grid_xo(h, gw, gw->O2, G.U, B); };
   auto gemm_v = [&]() {
     return rocblas_dgemm(gw->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)D.p_pad, B,
                          (rocblas_int)D.n, &one, h->X64, (rocblas_int)D.ldx, G.U, (rocblas_int)D.n, &zero, G.V,
