@@ -140,7 +140,11 @@ flr_status flr_solve_ex(flr_problem h, double lambda1, double lambda2, double to
  * its own scalars, weights, preconditioner and convergence state.
  * lambda1, lambda2: host, length B.  beta_out: host or device, B x p row-major.
  * res: nullable host array of B results.  Returns FLR_OK when every column
- * converged, else the first failing column's status. */
+ * converged, else the first failing column's status.
+ * With the banded preconditioner, a column that reaches an MM boundary may
+ * idle for up to 15 steps so that boundaries (one band factorization each)
+ * share launches; its arithmetic, and so its result, does not change.  The
+ * environment variable FLR_GRID_HOLD sets that period (1: no holding). */
 flr_status flr_solve_grid(flr_problem h, const double* lambda1, const double* lambda2, int32_t B, double tol,
                           const flr_solve_opts* opts, double* beta_out, flr_result* res);
 
