@@ -96,27 +96,22 @@ __device__ inline bool band_factor(double* __restrict__ Lb, double* __restrict__
         if (j >= p) break;
         const int dmax = (int)((p - 1 - j) < (int64_t)(W - 1) ? (p - 1 - j) : (int64_t)(W - 1));
         const double* cj = lds + jr * W;
+        // Every LDS read of the step is issued before the pivot's square root
+        // and reciprocal: the pivot, this thread's entry of column j (W <= nt,
+        // so one per thread), the column entries of its update pairs and the
+        // targets of those pairs.  Reads are unconditional at indices clamped
+        // into the column (a guarded load waits for itself); the rank-1 update
+        // of columns j+1 .. j+dmax gives thread (tx, ty) the pairs
+        // d1 = 1 + ty + 16 a (column), d2 = 1 + tx + 16 c (row), d1 <= d2, all
+        // distinct, so its targets are read before any is written.
         const double piv = cj[0];
-        if (!(piv > 0.0) || !isfinite(piv)) {
-          ok = false;
-          break;
-        }
-        const double ljj = sqrt(piv), inv = 1.0 / ljj;
-        for (int d = tid; d <= dmax; d += nt) {
-          const double v = d ? cj[d] * inv : ljj;
-          Lb[j * W + d] = d ? v * inv : ljj;
-          LbT[(j + d) * W + d] = v;
-        }
-        if (tid == 0) invd[j] = inv;
-        // rank-1 update of columns j+1 .. j+dmax: thread (tx, ty) owns the
-        // pairs d1 = 1 + ty + 16 a (column), d2 = 1 + tx + 16 c (row), d1 <= d2;
-        // all its targets are read before any is written (they are distinct)
-        double sr[kRingB], scl[kRingB], tv[kRingB][kRingB];
+        const double cown = cj[tid < W ? tid : W - 1];
+        double cr[kRingB], cc[kRingB], tv[kRingB][kRingB];
 #pragma unroll
         for (int a = 0; a < kRingB; ++a) {
           const int d = 1 + 16 * a;
-          sr[a] = d + tx <= dmax ? cj[d + tx] * inv : 0.0;
-          scl[a] = d + ty <= dmax ? cj[d + ty] * inv : 0.0;
+          cr[a] = cj[d + tx < W ? d + tx : W - 1];
+          cc[a] = cj[d + ty < W ? d + ty : W - 1];
         }
 #pragma unroll
         for (int a = 0; a < kRingB; ++a) {
@@ -128,6 +123,24 @@ __device__ inline bool band_factor(double* __restrict__ Lb, double* __restrict__
             const int d2 = 1 + tx + 16 * c;
             if (d1 <= d2 && d2 <= dmax) tv[a][c] = tgt[d2];
           }
+        }
+        if (!(piv > 0.0) || !isfinite(piv)) {
+          ok = false;
+          break;
+        }
+        const double ljj = sqrt(piv), inv = 1.0 / ljj;
+        if (tid <= dmax) {
+          const double v = tid ? cown * inv : ljj;
+          Lb[j * W + tid] = tid ? v * inv : ljj;
+          LbT[(j + tid) * W + tid] = v;
+        }
+        if (tid == 0) invd[j] = inv;
+        double sr[kRingB], scl[kRingB];
+#pragma unroll
+        for (int a = 0; a < kRingB; ++a) {
+          const int d = 1 + 16 * a;
+          sr[a] = d + tx <= dmax ? cr[a] * inv : 0.0;
+          scl[a] = d + ty <= dmax ? cc[a] * inv : 0.0;
         }
 #pragma unroll
         for (int a = 0; a < kRingB; ++a) {
