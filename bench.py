@@ -120,8 +120,8 @@ def main():
     ap.add_argument("--serve-tol", type=float, default=1e-6)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported (the multi-GPU layout is "
-              "described in DESIGN.md)" % args.gpus, file=sys.stderr)
+        print("bench.py: runs on one GPU only; --gpus %d is not supported (each GPU would take its own "
+              "share of lambda columns or requests; nothing here spans GPUs)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
