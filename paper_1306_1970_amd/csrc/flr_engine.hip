@@ -374,7 +374,7 @@ flr_status flr_create(flr_ctx ctx, const void* X, flr_dtype x_dtype, int64_t n, 
     return fail(FLR_ERR_INVALID_ARG, "unknown x_dtype");
   if (m < 0 || (m > 0 && !edges)) return fail(FLR_ERR_INVALID_ARG, "bad edge list");
   if (n > (int64_t)1 << 31 || p > (int64_t)kMaxBlocks * kBlk - 2048)
-    return fail(FLR_ERR_INVALID_ARG, "problem too large for this build (p <= 260000)");
+    return fail(FLR_ERR_INVALID_ARG, "problem too large: n <= 2^31 and p <= 260096 (1024 solver blocks of 256, less one A panel)");
   for (int64_t i = 0; i < n; ++i)
     if (!std::isfinite(y[i])) return fail(FLR_ERR_INVALID_ARG, "y has a non-finite value");
   // canonical unordered edge set

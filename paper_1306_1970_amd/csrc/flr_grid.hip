@@ -656,7 +656,7 @@ static flr_status grid_run(flr_problem h, const double* l1, const double* l2, in
   flr_solve_opts dflt;
   flr_default_opts(&dflt);
   if (!o) o = &dflt;
-  if (o->precision != FLR_PREC_FP64) return gfail(FLR_ERR_INVALID_ARG, "grid solves run in FP64 in this build");
+  if (o->precision != FLR_PREC_FP64) return gfail(FLR_ERR_INVALID_ARG, "grid solves run in FP64 (no mixed-precision grid path)");
   const bool want_band = h->band_w && (o->preconditioner == FLR_PRECOND_AUTO || o->preconditioner == FLR_PRECOND_BAND);
   flr_status ps = grid_prepare(h, B, want_band);
   if (ps != FLR_OK) return ps;

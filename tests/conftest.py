@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests need a visible device; on a CPU-only host they are skipped
-    # rather than failed, so "-m gpu" on the GPU machine is the real run.
+    # rather than failed, so "-m gpu" on a machine with a GPU is the real run.
     try:
         import torch
 
