@@ -65,7 +65,7 @@ typedef enum { FLR_PREC_FP64 = 0, FLR_PREC_MIXED_FP32 = 1 } flr_precision;
 /* Preconditioner of the PCG inner solve (Algorithm 2 uses M = lambda1 A +
  * lambda2 B itself).
  *   BAND    M exactly, through its banded Cholesky factor (bandwidth
- *           bw = max |j - k| over E, Section 3.2): for bw >= 2, i.e. the 2-D
+ *           bw = max |j - k| over E; section 3.1): for bw >= 2, i.e. the 2-D
  *           lattice (bw = q) and all-pairs fusion; one factorization per MM
  *           iteration, two sequential triangular sweeps per PCG step.
  *           Needs lambda1 > 0 and bw + 1 <= 1025.

@@ -10,9 +10,11 @@
  *  - PCG residual update: the paper prints r_j = r_{j-1} + nu Q p_j while
  *    starting from r_0 = c - Q x_0; with that sign CG diverges.  The
  *    standard recurrence r_j = r_{j-1} - nu Q p_j is used.
- *  - The inner test ||r||/||c|| <= delta_in is checked before every PCG
- *    step, including the first (a warm start that already solves the
- *    system takes zero steps, avoiding 0/0 in nu).
+ *  - The inner loop of Algorithm 2 is repeat-until: at least one PCG step
+ *    runs in every MM iteration, and the test ||r||/||c|| <= delta_in is
+ *    evaluated after each step.  The one exception is r_0 = 0 exactly (the
+ *    warm start solves the system in floating point): then nu would be 0/0,
+ *    and no step is taken.
  *  - Inner cap: p steps (the finite-termination bound of CG).
  *  - The outer test uses the true objective f (FLR objective), relative to
  *    the previous value: |f_new - f_old| / f_old <= delta.  delta = 0 runs
@@ -448,9 +450,12 @@ int ofl_solve(const ofl_problem* P, double l1, double l2, const ofl_opts* o, dou
       band_solve(Lb, p, bw, r, z);
       memcpy(pv, z, (size_t)p * sizeof(double));
       double rz = dot(r, z, p);
-      double rn = sqrt(dot(r, r, p)) / cnorm;
+      double rr0 = dot(r, r, p);
+      double rn = sqrt(rr0) / cnorm;
       int bad = 0;
-      while (rn > itol && cg < max_cg) {
+      /* repeat ... until ||r_j|| / ||X^T y|| <= delta_in (or the cap) */
+      int more = rr0 > 0.0 && max_cg > 0;
+      while (more) {
         gemv_x(xd, n, p, pv, u);
         gemv_xt(xd, n, p, u, q);
         apply_m(P, l1, l2, a, w, pv, t);
@@ -472,6 +477,7 @@ int ofl_solve(const ofl_problem* P, double l1, double l2, const ofl_opts* o, dou
         for (int64_t j = 0; j < p; ++j) pv[j] = z[j] + gamma * pv[j];
         rn = sqrt(dot(r, r, p)) / cnorm;
         ++cg;
+        more = rn > itol && cg < max_cg;
       }
       if (bad) {
         status = OFL_NUMERICAL;

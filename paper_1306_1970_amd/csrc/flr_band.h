@@ -1,8 +1,9 @@
 // Exact preconditioner solve for graphs whose index bandwidth bw = max |j - k|
 // over E is at least 2 (the 2-D lattice, all-pairs fusion): M = lambda1 A +
 // lambda2 B is banded with bandwidth bw, and Algorithm 2 applies M^-1 through
-// its banded Cholesky factor M = L L^T (Section 3.2; the lattice in the
-// paper's 2-D experiments has bw = q).  M changes once per MM iteration, so
+// its banded Cholesky factor M = L L^T (section 3.1, where the PCG
+// preconditioner is solved with a banded Cholesky factorization; the lattice
+// of the paper's 2-D experiments has bw = q).  M changes once per MM iteration, so
 // the factor is computed once per MM iteration and every PCG step applies it
 // with two triangular sweeps.
 //
@@ -201,6 +202,10 @@ __device__ inline bool band_factor(double* __restrict__ Lb, double* __restrict__
       __syncthreads();
     }
   }
+  // the rescale below reads invd (stored by thread 0) and LbT entries stored
+  // by other threads: a full barrier orders those global stores (the ring
+  // loop's last barrier orders LDS only)
+  __syncthreads();
   if (ok) {  // rows of L scaled by their own 1/L_ii (the backward sweep's multipliers)
     const int64_t tot = p * (int64_t)W;
     for (int64_t idx = tid; idx < tot; idx += nt) {

@@ -354,7 +354,9 @@ __global__ __launch_bounds__(kWG) void k_col(GridDev G, int hold) {
     }
   } else {
     s.rz = rz;
-    const bool done = !(rn > prm.inner_tol) || prm.max_cg <= 0;
+    // Algorithm 2's inner loop is repeat-until: at least one PCG step after
+    // r0, unless r0 is exactly zero (nu would be 0/0)
+    const bool done = !(rr > 0.0);
     if (done) {
       s.phase = PH_END;
       for (int64_t j = tid; j < P; j += kWG) O[j] = j < p ? x[j] : 0.0;
@@ -473,6 +475,7 @@ struct GridWork {
   double* Upart = nullptr;    // splitk x n x cap partial products
   int32_t* d_map = nullptr;   // cap
   int32_t* d_from = nullptr;  // cap
+  size_t bytes = 0;           // device bytes of this workspace, charged to the problem's footprint
 };
 
 namespace flr {
@@ -504,6 +507,7 @@ void grid_free(flr_problem h) {
   for (void* p : gw->allocs) (void)hipFree(p);
   if (gw->h_st) (void)hipHostFree(gw->h_st);
   if (gw->ev) (void)hipEventDestroy(gw->ev);
+  h->footprint -= gw->bytes;
   delete gw;
   h->grid = nullptr;
 }
@@ -527,6 +531,7 @@ static flr_status grid_prepare(flr_problem h, int B, bool band) {
   const Dims& D = h->D;
   if (!h->X64) {
     GCK(hipMalloc(reinterpret_cast<void**>(&h->X64), (size_t)D.n * (size_t)D.ldx * sizeof(double)));
+    h->footprint += (size_t)D.n * (size_t)D.ldx * sizeof(double);
     const int64_t cnt = D.n * D.ldx;
     switch (D.dtype) {
       case 0:
@@ -545,6 +550,7 @@ static flr_status grid_prepare(flr_problem h, int B, bool band) {
   }
   if (!h->X64c) {
     GCK(hipMalloc(reinterpret_cast<void**>(&h->X64c), (size_t)D.n * (size_t)D.p_pad * sizeof(double)));
+    h->footprint += (size_t)D.n * (size_t)D.p_pad * sizeof(double);
     const dim3 tg((unsigned)(D.p_pad / 64), (unsigned)((D.n + 63) / 64));
     switch (D.dtype) {
       case 0:
@@ -569,6 +575,8 @@ static flr_status grid_prepare(flr_problem h, int B, bool band) {
       for (double** ptr : {&gw->G.Lb, &gw->G.LbT}) {
         GCK(hipMalloc(reinterpret_cast<void**>(ptr), nb * sizeof(double)));
         gw->allocs.push_back(*ptr);
+        gw->bytes += nb * sizeof(double);
+        h->footprint += nb * sizeof(double);
         GCK(hipMemsetAsync(*ptr, 0, nb * sizeof(double), h->stream));
       }
     }
@@ -582,6 +590,8 @@ static flr_status grid_prepare(flr_problem h, int B, bool band) {
     hipError_t e = hipMalloc(reinterpret_cast<void**>(ptr), std::max<size_t>(cnt, 1) * sizeof(double));
     if (e == hipSuccess) {
       gw->allocs.push_back(*ptr);
+      gw->bytes += std::max<size_t>(cnt, 1) * sizeof(double);
+      h->footprint += std::max<size_t>(cnt, 1) * sizeof(double);
       e = hipMemsetAsync(*ptr, 0, std::max<size_t>(cnt, 1) * sizeof(double), h->stream);
     }
     return e;

@@ -514,7 +514,9 @@ __device__ void combine_blocks_wave(const Dims& D, const Bufs& B, const Params& 
   const double rr = wave_sum(rrp);
   if (l == 0) {
     const double rn = sqrt(rr) / prm.cnorm;
-    const bool done = !(rn > prm.inner_tol) || o.cg_iter >= prm.max_cg;
+    // Algorithm 2's inner loop is repeat-until: after r0 (first_step) at least
+    // one PCG step runs unless r0 is exactly zero (nu would be 0/0)
+    const bool done = first_step ? !(rr > 0.0) : (!(rn > prm.inner_tol) || o.cg_iter >= prm.max_cg);
     o.rel_res = rn;
     o.rz = rz;
     o.gamma = first_step ? 0.0 : rz / rz_prev;
@@ -603,7 +605,9 @@ __device__ void combine_blocks(const Dims& D, const Bufs& B, const Params& prm, 
   const double rr = wg_sum(rrp, sh_m + 8);
   if (tid == 0) {
     const double rn = sqrt(rr) / prm.cnorm;
-    const bool done = !(rn > prm.inner_tol) || o.cg_iter >= prm.max_cg;
+    // Algorithm 2's inner loop is repeat-until: after r0 (first_step) at least
+    // one PCG step runs unless r0 is exactly zero (nu would be 0/0)
+    const bool done = first_step ? !(rr > 0.0) : (!(rn > prm.inner_tol) || o.cg_iter >= prm.max_cg);
     o.rel_res = rn;
     o.rz = rz;
     o.gamma = first_step ? 0.0 : rz / rz_prev;
@@ -870,7 +874,8 @@ __global__ __launch_bounds__(kWG) void k_band(Dims D, Bufs B, const State* __res
   wg_sum4(sums, red);
   if (tid == 0) {
     const double rz = sums[0], rn = sqrt(sums[1]) / prm.cnorm;
-    const bool done = !(rn > prm.inner_tol) || (mm ? prm.max_cg <= 0 : o.cg_iter >= prm.max_cg);
+    // repeat-until: after r0 at least one PCG step, unless r0 is exactly zero
+    const bool done = mm ? !(sums[1] > 0.0) : (!(rn > prm.inner_tol) || o.cg_iter >= prm.max_cg);
     o.rel_res = rn;
     o.gamma = mm ? 0.0 : rz / s.rz;
     o.rz = rz;

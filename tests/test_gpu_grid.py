@@ -183,3 +183,19 @@ def test_grid_lattice_held_boundaries(flr, ctx, monkeypatch):
         # between the schedules), so the two agree to rounding, not bit for bit
         assert abs(res[b]["cg_iters"] - res1[b]["cg_iters"]) <= 2
         assert err <= 1e-8 and err1 <= 1e-10
+
+
+def test_grid_workspace_is_charged_to_footprint(flr, ctx):
+    # serving admission charges flr_problem_footprint: the grid workspace a handle keeps after a
+    # grid solve (per-column vectors, products, band factors) must be part of it
+    inst = flrgen.small_instance(40, 144, "lattice", dtype=flrgen.F32, seed=37)
+    prob = flr.Problem.from_instance(ctx, inst)
+    before = prob.footprint
+    l1, l2 = np.array([0.1, 0.5, 1.0, 2.0]), np.array([0.2, 0.2, 0.3, 0.4])
+    prob.solve_grid(l1, l2, tol=1e-5)
+    after = prob.footprint
+    print("  footprint %d -> %d bytes" % (before, after), flush=True)
+    # at least the four columns' banded factors (by columns and by rows) and eight p-vectors each
+    W = inst.meta["q"] + 1
+    assert after - before >= 4 * (2 * inst.p * W + 8 * inst.p) * 8
+    prob.close()
