@@ -15,7 +15,7 @@ Workloads (--workload):
   c4  n=5000, p=50000, X stored BF16, y FP32
   c3  batched grid: two-dimensional FLR on the 100 x 100 lattice, n=2000,
       X FP32, the 16 x 16 log-spaced (lambda1, lambda2) grid over [0.01, 10]
-      solved in one batched solve (FP64 GEMMs for X O and X^T U); a sample of
+      solved in one batched solve (FP64 matrix-core products X O and X^T U); a sample of
       the same columns through the plain single-solve path gives the plain
       solves/s beside it (a separate line, not the headline)
   c5  serving stream: Poisson arrivals of mixed requests (p in {1k, 5k, 10k,
@@ -276,7 +276,7 @@ def grid_main(args, flr):
                    "max_objective_gap_vs_plain": max(gaps) if gaps else None,
                    "status": int(st), "mm_iters_max": max(r["mm_iters"] for r in res),
                    "cg_iters_max": max(r["cg_iters"] for r in res)},
-        "roofline": {"bound": "mfma", "kernel": "dgemm_XO" if ua >= va else "dgemm_XtU", "achieved": achieved,
+        "roofline": {"bound": "mfma", "kernel": "gemm_XO" if ua >= va else "gemm_XtU", "achieved": achieved,
                      "peak": 78.6, "unit": "TFLOP/s", "frac": achieved / 78.6, "traffic": None,
                      "avg_us": dom_us, "algorithmic_flops": flops, "other_kernel_us": min(ua, va)},
     }

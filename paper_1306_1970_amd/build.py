@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libflr.so")
-SOURCES = ["flr_kernels.hip", "flr_engine.hip", "flr_grid.hip", "flr_server.hip"]
+SOURCES = ["flr_kernels.hip", "flr_engine.hip", "flr_grid.hip", "flr_gemm.hip", "flr_server.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC", "-Wall", "-Wno-unused-function",
@@ -40,8 +40,7 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
     while procs:
         _wait(procs.pop(0), verbose)
     tmp = SO + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs, "-L/opt/rocm/lib", "-lrocblas",
-           "-Wl,-rpath,/opt/rocm/lib"]
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -350,8 +350,6 @@ static void problem_free(flr_problem h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   flr::grid_free(h);
-  if (h->X64) (void)hipFree(h->X64);
-  if (h->X64c) (void)hipFree(h->X64c);
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) {
       if (h->gexec[a][b]) (void)hipGraphExecDestroy(h->gexec[a][b]);

@@ -4,7 +4,8 @@
 // each PCG step become dense GEMMs over all columns:
 //   U = X O^T   (n x B)      O[b] = p_b in a PCG step, x_b at an MM boundary
 //   V = X^T U   (p x B)
-// run as FP64 rocBLAS GEMMs (plain library GEMMs on the matrix cores).
+// run as FP64 matrix-core products that read X in its stored type
+// (flr_gemm.hip).
 // Everything else of a step is one fused kernel per column (k_col, one
 // workgroup owns one column): the Laplacian product, p^T Q p, the CG updates,
 // the whole tridiagonal preconditioner solve as a chunked two-level scan, the
@@ -13,7 +14,6 @@
 // their own pace: each keeps its own phase; finished columns contribute zero
 // operands.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -26,6 +26,7 @@
 
 #include "flr_band.h"
 #include "flr_device.h"
+#include "flr_gemm.h"
 #include "flr_problem.h"
 
 namespace flr {
@@ -45,6 +46,7 @@ struct GridParams {
 
 struct GridDev {
   int64_t n, p, p_pad, nnz;
+  int64_t ldu;   // leading dimension of U (n rounded up to the product tile)
   int32_t B, pad;
   const double* y;
   const double* c;
@@ -58,7 +60,7 @@ struct GridDev {
   double* g;
   double* z;
   double* O;     // GEMM operand, B x p_pad (column-major p_pad x B)
-  double* U;     // n x B (column-major, ld n)
+  double* U;     // n x B (column-major, ld ldu)
   double* V;     // p_pad x B (column-major, ld p_pad)
   double* a;
   double* d;
@@ -209,7 +211,7 @@ __global__ __launch_bounds__(kWG) void k_col(GridDev G, int hold) {
   double* z = G.z + off;
   double* O = G.O + (int64_t)slot * P;
   const double* V = G.V + (int64_t)slot * P;
-  const double* U = G.U + (int64_t)slot * G.n;
+  const double* U = G.U + (int64_t)slot * G.ldu;
 
   const bool cg = s.phase == PH_CG;
   if (cg) {
@@ -406,45 +408,6 @@ __global__ __launch_bounds__(kWG) void k_gather_cols(const double* __restrict__ 
   if (j < P) Onew[(int64_t)t * P + j] = Oold[(int64_t)from[t] * P + j];
 }
 
-template <typename XT>
-__global__ __launch_bounds__(kWG) void k_widen(const XT* __restrict__ X, double* __restrict__ X64, int64_t count) {
-  const int64_t stride = (int64_t)gridDim.x * kWG;
-  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < count; i += stride) {
-    if constexpr (sizeof(XT) == 2) {
-      X64[i] = (double)__uint_as_float(((uint32_t)X[i]) << 16);
-    } else {
-      X64[i] = (double)X[i];
-    }
-  }
-}
-
-// Column-major FP64 copy of X (n x p_pad, leading dimension n), so that
-// U = X O is a plain (N, N) GEMM: 64 x 64 tiles through LDS, reads along the
-// rows of the stored X and writes along its columns, both coalesced.
-template <typename XT>
-__global__ __launch_bounds__(kWG) void k_transpose64(const XT* __restrict__ X, double* __restrict__ Xc, int64_t n,
-                                                     int64_t ldx) {
-  __shared__ double tile[64][65];
-  const int64_t i0 = (int64_t)blockIdx.y * 64, j0 = (int64_t)blockIdx.x * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int r = ty; r < 64; r += 4) {
-    const int64_t i = i0 + r, j = j0 + tx;
-    double v = 0.0;
-    if (i < n) {
-      if constexpr (sizeof(XT) == 2)
-        v = (double)__uint_as_float(((uint32_t)X[i * ldx + j]) << 16);
-      else
-        v = (double)X[i * ldx + j];
-    }
-    tile[r][tx] = v;
-  }
-  __syncthreads();
-  for (int c = ty; c < 64; c += 4) {
-    const int64_t j = j0 + c, i = i0 + tx;
-    if (i < n) Xc[j * n + i] = tile[tx][c];
-  }
-}
-
 // U = sum of the split-K partial products, in slice order (fixed, so the
 // result does not depend on timing).
 __global__ __launch_bounds__(kWG) void k_sum_parts(const double* __restrict__ parts, double* __restrict__ out,
@@ -460,58 +423,180 @@ __global__ __launch_bounds__(kWG) void k_sum_parts(const double* __restrict__ pa
 
 using namespace flr;
 
+// The whole device workspace of a grid solve is one block: the allocating
+// entry point takes it from hipMalloc (kept on the handle and charged to its
+// footprint), the no-allocation entry point from a static device array.
+// GridCarve places every buffer in it (256-byte aligned); run with a null
+// base it only measures.
+struct GridCarve {
+  char* base = nullptr;
+  size_t used = 0;
+  template <typename T>
+  T* take(size_t count) {
+    const size_t b = (std::max<size_t>(count, 1) * sizeof(T) + 255) & ~(size_t)255;
+    T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
+    used += b;
+    return p;
+  }
+};
+
 struct GridWork {
-  int cap = 0;
+  int cap = 0;                // columns the workspace holds
+  bool band = false;          // holds a banded factor per column
   GridDev G{};
-  rocblas_handle blas = nullptr;
-  std::vector<void*> allocs;
+  char* block = nullptr;      // device workspace
+  size_t bytes = 0;
+  bool owned = false;         // block from hipMalloc (freed with the handle)
   GridParams* d_prm = nullptr;
-  double* d_lam = nullptr;   // 2 x cap
-  int32_t* d_jac = nullptr;  // cap
-  ColState* h_st = nullptr;  // pinned, cap
-  hipEvent_t ev = nullptr;
-  double* O2 = nullptr;       // second operand buffer for compaction
-  int splitk = 1;             // K slices of U = X O
-  double* Upart = nullptr;    // splitk x n x cap partial products
+  double* d_lam = nullptr;    // 2 x cap
+  int32_t* d_jac = nullptr;   // cap
   int32_t* d_map = nullptr;   // cap
   int32_t* d_from = nullptr;  // cap
-  size_t bytes = 0;           // device bytes of this workspace, charged to the problem's footprint
+  double* O2 = nullptr;       // second operand buffer for compaction
+  int splitk = 1;             // K slices of U = X O
+  double* Upart = nullptr;    // splitk x ldu x cap partial products
+  ColState* h_st = nullptr;   // host copy of the column states (pinned on the allocating path)
+  hipEvent_t ev = nullptr;    // polling event (allocating path; the no-allocation path synchronizes)
 };
 
 namespace flr {
-// U = X O (column-major n x nact) from the column-major copy of X, split
-// over K into gw->splitk slices when that fills the chip better.
-static rocblas_status grid_xo(flr_problem h, GridWork* gw, const double* O, double* U, int nact) {
+
+// K slices of U = X O: a product over all p columns has only ceil(n/64)
+// row tiles per 64 columns, so it is split over K until about 256 row-band
+// tiles exist (slices of at least 512, a multiple of the K tile).  Fixed per
+// problem shape, so a column's products never depend on the batch.
+static int grid_splitk(const Dims& D) {
+  const int64_t tm = (D.n + kGemmMT - 1) / kGemmMT;
+  int sk = 1;
+  while (sk < 8 && tm * sk * 2 <= 256 && D.p_pad % ((int64_t)sk * 2 * kGemmKT) == 0 && D.p_pad / (sk * 2) >= 512)
+    sk *= 2;
+  return sk;
+}
+
+static void grid_carve(GridCarve& c, GridWork& gw, const Dims& D, int cap, int64_t nnz, int band_w, bool band) {
+  GridDev& G = gw.G;
+  const size_t PB = (size_t)D.p_pad * (size_t)cap;
+  const int64_t ldu = (D.n + kGemmMT - 1) / kGemmMT * kGemmMT;
+  G.ldu = ldu;
+  G.x = c.take<double>(PB);
+  G.r = c.take<double>(PB);
+  G.pv = c.take<double>(PB);
+  G.g = c.take<double>(PB);
+  G.z = c.take<double>(PB);
+  G.O = c.take<double>(PB);
+  gw.O2 = c.take<double>(PB);
+  G.V = c.take<double>(PB);
+  G.a = c.take<double>(PB);
+  G.d = c.take<double>(PB);
+  G.e = c.take<double>(PB);
+  G.L = c.take<double>(PB);
+  G.invD = c.take<double>(PB);
+  G.U = c.take<double>((size_t)ldu * (size_t)cap);
+  G.w = c.take<double>((size_t)std::max<int64_t>(nnz, 1) * (size_t)cap);
+  gw.splitk = grid_splitk(D);
+  gw.Upart = gw.splitk > 1 ? c.take<double>((size_t)gw.splitk * (size_t)ldu * (size_t)cap) : nullptr;
+  if (band) {
+    G.Lb = c.take<double>((size_t)cap * (size_t)D.p * (size_t)band_w);
+    G.LbT = c.take<double>((size_t)cap * (size_t)D.p * (size_t)band_w);
+  } else {
+    G.Lb = G.LbT = nullptr;
+  }
+  gw.d_lam = c.take<double>(2 * (size_t)cap);
+  G.st = c.take<ColState>((size_t)cap);
+  gw.d_prm = c.take<GridParams>(1);
+  gw.d_jac = c.take<int32_t>((size_t)cap);
+  gw.d_map = c.take<int32_t>((size_t)cap);
+  gw.d_from = c.take<int32_t>((size_t)cap);
+}
+
+// Static fields of the column view for a problem.
+static void grid_bind(GridWork& gw, flr_problem h) {
+  GridDev& G = gw.G;
   const Dims& D = h->D;
-  const double one = 1.0, zero = 0.0;
-  const int sk = gw->splitk;
-  if (sk <= 1)
-    return rocblas_dgemm(gw->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)D.n, nact,
-                         (rocblas_int)D.p_pad, &one, h->X64c, (rocblas_int)D.n, O, (rocblas_int)D.p_pad, &zero, U,
-                         (rocblas_int)D.n);
-  const int64_t kc = D.p_pad / sk, cnt = D.n * (int64_t)nact;
-  const rocblas_status st = rocblas_dgemm_strided_batched(
-      gw->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)D.n, nact, (rocblas_int)kc, &one,
-      h->X64c, (rocblas_int)D.n, (rocblas_stride)(kc * D.n), O, (rocblas_int)D.p_pad, (rocblas_stride)kc, &zero,
-      gw->Upart, (rocblas_int)D.n, (rocblas_stride)cnt, sk);
-  if (st != rocblas_status_success) return st;
-  hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((cnt + kWG - 1) / kWG)), dim3(kWG), 0, h->stream, gw->Upart, U,
-                     cnt, sk);
-  return hipGetLastError() == hipSuccess ? rocblas_status_success : rocblas_status_internal_error;
+  G.n = D.n;
+  G.p = D.p;
+  G.p_pad = D.p_pad;
+  G.nnz = std::max<int64_t>(h->nnz, 1);
+  G.y = h->B.y;
+  G.c = h->B.c;
+  G.s = h->B.s;
+  G.rowptr = h->B.rowptr;
+  G.col = h->B.col;
+  G.prevpos = h->B.prevpos;
+  G.prm = gw.d_prm;
+  G.map = gw.d_map;
+}
+
+// Workspace bytes of a grid solve with `cap` columns on this problem.
+size_t grid_workspace_bytes(flr_problem h, int cap, bool band) {
+  GridCarve c;
+  GridWork gw;
+  grid_carve(c, gw, h->D, cap, h->nnz, h->band_w, band);
+  return c.used;
 }
 
 void grid_free(flr_problem h) {
   GridWork* gw = h->grid;
   if (!gw) return;
-  if (gw->blas) rocblas_destroy_handle(gw->blas);
-  for (void* p : gw->allocs) (void)hipFree(p);
+  if (gw->owned && gw->block) {
+    (void)hipFree(gw->block);
+    h->footprint -= gw->bytes;
+  }
   if (gw->h_st) (void)hipHostFree(gw->h_st);
   if (gw->ev) (void)hipEventDestroy(gw->ev);
-  h->footprint -= gw->bytes;
   delete gw;
   h->grid = nullptr;
 }
 bool is_device_pointer(const void* p);
+
+__global__ __launch_bounds__(kWG) void k_fill_zero(double* __restrict__ p, int64_t count) {
+  const int64_t stride = (int64_t)gridDim.x * kWG;
+  for (int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x; i < count; i += stride) p[i] = 0.0;
+}
+
+// U = X O, then V = X^T U, for the first nact operand columns.
+static hipError_t grid_products(flr_problem h, const GridWork& gw, const GridDev& G, const double* O, int nact) {
+  const Dims& D = h->D;
+  GemmArgs a{};
+  a.X = h->B.X;
+  a.ldx = D.ldx;
+  a.Bm = O;
+  a.ldb = D.p_pad;
+  a.C = gw.splitk > 1 ? gw.Upart : G.U;
+  a.ldc = G.ldu;
+  a.cslice = G.ldu * (int64_t)nact;
+  a.M = (int32_t)D.n;
+  a.N = nact;
+  a.K = (int32_t)(D.p_pad / gw.splitk);
+  a.tiles_m = (int32_t)((D.n + kGemmMT - 1) / kGemmMT);
+  a.tiles_n = (nact + kGemmNT - 1) / kGemmNT;
+  a.nslice = gw.splitk;
+  hipError_t e = launch_gemm_xo(D.dtype, a, h->stream);
+  if (e != hipSuccess) return e;
+  if (gw.splitk > 1) {
+    const int64_t cnt = G.ldu * (int64_t)nact;
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((cnt + kWG - 1) / kWG)), dim3(kWG), 0, h->stream, gw.Upart, G.U,
+                       cnt, gw.splitk);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  GemmArgs b{};
+  b.X = h->B.X;
+  b.ldx = D.ldx;
+  b.Bm = G.U;
+  b.ldb = G.ldu;
+  b.C = G.V;
+  b.ldc = D.p_pad;
+  b.cslice = 0;
+  b.M = (int32_t)D.p_pad;
+  b.N = nact;
+  b.K = (int32_t)D.n;
+  b.tiles_m = (int32_t)(D.p_pad / kGemmMT);
+  b.tiles_n = (nact + kGemmNT - 1) / kGemmNT;
+  b.nslice = 1;
+  return launch_gemm_xtu(D.dtype, b, h->stream);
+}
+
 }  // namespace flr
 
 static flr_status gfail(flr_status st, const std::string& m) {
@@ -527,150 +612,45 @@ static flr_status gfail(flr_status st, const std::string& m) {
                    std::string(#expr) + ": " + hipGetErrorString(e_));                                      \
   } while (0)
 
+// Workspace of the allocating entry point: kept on the handle while it holds
+// at least B columns (and a banded factor when one is needed), else replaced.
 static flr_status grid_prepare(flr_problem h, int B, bool band) {
-  const Dims& D = h->D;
-  if (!h->X64) {
-    GCK(hipMalloc(reinterpret_cast<void**>(&h->X64), (size_t)D.n * (size_t)D.ldx * sizeof(double)));
-    h->footprint += (size_t)D.n * (size_t)D.ldx * sizeof(double);
-    const int64_t cnt = D.n * D.ldx;
-    switch (D.dtype) {
-      case 0:
-        GCK(hipMemcpyAsync(h->X64, h->B.X, (size_t)cnt * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
-        break;
-      case 1:
-        hipLaunchKernelGGL(k_widen<float>, dim3(2048), dim3(kWG), 0, h->stream,
-                           reinterpret_cast<const float*>(h->B.X), h->X64, cnt);
-        break;
-      default:
-        hipLaunchKernelGGL(k_widen<uint16_t>, dim3(2048), dim3(kWG), 0, h->stream,
-                           reinterpret_cast<const uint16_t*>(h->B.X), h->X64, cnt);
-        break;
-    }
-    GCK(hipGetLastError());
-  }
-  if (!h->X64c) {
-    GCK(hipMalloc(reinterpret_cast<void**>(&h->X64c), (size_t)D.n * (size_t)D.p_pad * sizeof(double)));
-    h->footprint += (size_t)D.n * (size_t)D.p_pad * sizeof(double);
-    const dim3 tg((unsigned)(D.p_pad / 64), (unsigned)((D.n + 63) / 64));
-    switch (D.dtype) {
-      case 0:
-        hipLaunchKernelGGL(k_transpose64<double>, tg, dim3(kWG), 0, h->stream,
-                           reinterpret_cast<const double*>(h->B.X), h->X64c, D.n, D.ldx);
-        break;
-      case 1:
-        hipLaunchKernelGGL(k_transpose64<float>, tg, dim3(kWG), 0, h->stream,
-                           reinterpret_cast<const float*>(h->B.X), h->X64c, D.n, D.ldx);
-        break;
-      default:
-        hipLaunchKernelGGL(k_transpose64<uint16_t>, tg, dim3(kWG), 0, h->stream,
-                           reinterpret_cast<const uint16_t*>(h->B.X), h->X64c, D.n, D.ldx);
-        break;
-    }
-    GCK(hipGetLastError());
-  }
-  if (h->grid && h->grid->cap >= B) {
-    if (band && !h->grid->G.Lb) {
-      GridWork* gw = h->grid;
-      const size_t nb = (size_t)gw->cap * (size_t)D.p * (size_t)h->band_w;
-      for (double** ptr : {&gw->G.Lb, &gw->G.LbT}) {
-        GCK(hipMalloc(reinterpret_cast<void**>(ptr), nb * sizeof(double)));
-        gw->allocs.push_back(*ptr);
-        gw->bytes += nb * sizeof(double);
-        h->footprint += nb * sizeof(double);
-        GCK(hipMemsetAsync(*ptr, 0, nb * sizeof(double), h->stream));
-      }
-    }
-    return FLR_OK;
-  }
+  if (h->grid && h->grid->cap >= B && (h->grid->band || !band)) return FLR_OK;
   grid_free(h);
   GridWork* gw = new GridWork;
   h->grid = gw;
   gw->cap = B;
-  auto al = [&](double** ptr, size_t cnt) -> hipError_t {
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(ptr), std::max<size_t>(cnt, 1) * sizeof(double));
-    if (e == hipSuccess) {
-      gw->allocs.push_back(*ptr);
-      gw->bytes += std::max<size_t>(cnt, 1) * sizeof(double);
-      h->footprint += std::max<size_t>(cnt, 1) * sizeof(double);
-      e = hipMemsetAsync(*ptr, 0, std::max<size_t>(cnt, 1) * sizeof(double), h->stream);
-    }
-    return e;
-  };
-  GridDev& G = gw->G;
-  const size_t PB = (size_t)D.p_pad * (size_t)B;
-  GCK(al(&G.x, PB));
-  GCK(al(&G.r, PB));
-  GCK(al(&G.pv, PB));
-  GCK(al(&G.g, PB));
-  GCK(al(&G.z, PB));
-  GCK(al(&G.O, PB));
-  GCK(al(&gw->O2, PB));
-  GCK(al(&G.V, PB));
-  GCK(al(&G.U, (size_t)D.n * (size_t)B));
-  GCK(al(&G.a, PB));
-  GCK(al(&G.d, PB));
-  GCK(al(&G.e, PB));
-  GCK(al(&G.L, PB));
-  GCK(al(&G.invD, PB));
-  GCK(al(&G.w, (size_t)std::max<int64_t>(h->nnz, 1) * (size_t)B));
-  if (band) {
-    GCK(al(&G.Lb, (size_t)B * (size_t)D.p * (size_t)h->band_w));
-    GCK(al(&G.LbT, (size_t)B * (size_t)D.p * (size_t)h->band_w));
-  }
-  {
-    // U = X O has an n x B output, a few dozen 128 x 128 tiles when n is a few
-    // thousand, each walking all of K = p_pad: split K so the product fills
-    // the chip (up to 512 tiles, slices of at least 1024)
-    const int64_t tiles = ((D.n + 127) / 128) * (((int64_t)B + 127) / 128);
-    int sk = 1;
-    while (sk < 8 && tiles * sk * 2 <= 512 && D.p_pad % (sk * 2 * 64) == 0 && D.p_pad / (sk * 2) >= 1024) sk *= 2;
-    gw->splitk = sk;
-    if (sk > 1) GCK(al(&gw->Upart, (size_t)sk * (size_t)D.n * (size_t)B));
-  }
-  GCK(al(&gw->d_lam, 2 * (size_t)B));
-  double* tmp = nullptr;
-  GCK(al(&tmp, (sizeof(ColState) * (size_t)B + 7) / 8));
-  G.st = reinterpret_cast<ColState*>(tmp);
-  GCK(al(&tmp, (sizeof(GridParams) + 7) / 8));
-  gw->d_prm = reinterpret_cast<GridParams*>(tmp);
-  GCK(al(&tmp, ((size_t)B * sizeof(int32_t) + 7) / 8));
-  gw->d_jac = reinterpret_cast<int32_t*>(tmp);
-  GCK(al(&tmp, ((size_t)B * sizeof(int32_t) + 7) / 8));
-  gw->d_map = reinterpret_cast<int32_t*>(tmp);
-  GCK(al(&tmp, ((size_t)B * sizeof(int32_t) + 7) / 8));
-  gw->d_from = reinterpret_cast<int32_t*>(tmp);
+  gw->band = band;
+  GridCarve c;
+  grid_carve(c, *gw, h->D, B, h->nnz, h->band_w, band);
+  gw->bytes = c.used;
+  GCK(hipMalloc(reinterpret_cast<void**>(&gw->block), gw->bytes));
+  gw->owned = true;
+  h->footprint += gw->bytes;
+  c.base = gw->block;
+  c.used = 0;
+  grid_carve(c, *gw, h->D, B, h->nnz, h->band_w, band);
+  grid_bind(*gw, h);
+  hipLaunchKernelGGL(k_fill_zero, dim3(1024), dim3(kWG), 0, h->stream, reinterpret_cast<double*>(gw->block),
+                     (int64_t)(gw->bytes / sizeof(double)));
+  GCK(hipGetLastError());
   GCK(hipHostMalloc(reinterpret_cast<void**>(&gw->h_st), sizeof(ColState) * (size_t)B, hipHostMallocDefault));
   GCK(hipEventCreateWithFlags(&gw->ev, hipEventDisableTiming));
-  if (rocblas_create_handle(&gw->blas) != rocblas_status_success) return gfail(FLR_ERR_DEVICE, "rocblas_create_handle");
-  rocblas_set_stream(gw->blas, h->stream);
-  G.n = D.n;
-  G.p = D.p;
-  G.p_pad = D.p_pad;
-  G.nnz = std::max<int64_t>(h->nnz, 1);
-  G.y = h->B.y;
-  G.c = h->B.c;
-  G.s = h->B.s;
-  G.rowptr = h->B.rowptr;
-  G.col = h->B.col;
-  G.prevpos = h->B.prevpos;
-  G.lam1 = gw->d_lam;
-  G.lam2 = gw->d_lam + B;
-  G.prm = gw->d_prm;
-  G.map = gw->d_map;
   return FLR_OK;
 }
 
-static flr_status grid_run(flr_problem h, const double* l1, const double* l2, int32_t B, double tol,
-                           const flr_solve_opts* o, double* beta_out, flr_result* res) {
+// Host-side arrays of a grid solve (B entries each).
+struct GridHost {
+  double* lam;   // 2B
+  int32_t* jac;
+  int32_t* act;
+  int32_t* nxt;
+  int32_t* from;
+};
+
+static flr_status grid_run(flr_problem h, GridWork* gw, GridHost hb, const double* l1, const double* l2, int32_t B,
+                           double tol, const flr_solve_opts* o, double* beta_out, flr_result* res) {
   auto t0 = std::chrono::steady_clock::now();
-  flr_solve_opts dflt;
-  flr_default_opts(&dflt);
-  if (!o) o = &dflt;
-  if (o->precision != FLR_PREC_FP64) return gfail(FLR_ERR_INVALID_ARG, "grid solves run in FP64 (no mixed-precision grid path)");
-  const bool want_band = h->band_w && (o->preconditioner == FLR_PRECOND_AUTO || o->preconditioner == FLR_PRECOND_BAND);
-  flr_status ps = grid_prepare(h, B, want_band);
-  if (ps != FLR_OK) return ps;
-  GridWork* gw = h->grid;
   GridDev G = gw->G;
   G.B = B;
   const Dims& D = h->D;
@@ -681,44 +661,33 @@ static flr_status grid_run(flr_problem h, const double* l1, const double* l2, in
   P.cnorm = h->cnorm > 0.0 ? h->cnorm : 1.0;
   P.max_iter = o->max_iter > 0 ? o->max_iter : 10000;
   P.max_cg = o->max_cg > 0 ? o->max_cg : (int32_t)std::min<int64_t>(D.p, INT32_MAX);
-  std::vector<double> lam((size_t)2 * B);
-  std::vector<int32_t> jac((size_t)B);
   const int pre0 = o->preconditioner;
-  if (pre0 < FLR_PRECOND_AUTO || pre0 > FLR_PRECOND_BAND) return gfail(FLR_ERR_INVALID_ARG, "unknown preconditioner");
-  if (pre0 == FLR_PRECOND_BAND && !h->band_w)
-    return gfail(FLR_ERR_INVALID_ARG, "banded preconditioner: the edge set has bandwidth < 2 or its band is too wide");
-  const bool band = h->band_w && (pre0 == FLR_PRECOND_AUTO || pre0 == FLR_PRECOND_BAND);
+  const bool band = gw->band;
   for (int i = 0; i < B; ++i) {
-    lam[(size_t)i] = l1[i];
-    lam[(size_t)B + i] = l2[i];
+    hb.lam[i] = l1[i];
+    hb.lam[B + i] = l2[i];
     int pre = pre0;
     if (pre == FLR_PRECOND_AUTO) pre = l1[i] > 0.0 ? FLR_PRECOND_TRIDIAG : FLR_PRECOND_JACOBI;
     if ((pre == FLR_PRECOND_TRIDIAG || pre == FLR_PRECOND_BAND) && !(l1[i] > 0.0))
       return gfail(FLR_ERR_INVALID_ARG, "the tridiagonal and banded preconditioners need lambda1 > 0");
-    jac[(size_t)i] = pre == FLR_PRECOND_JACOBI ? 1 : 0;
+    hb.jac[i] = pre == FLR_PRECOND_JACOBI ? 1 : 0;
   }
   P.band = band ? h->band_w : 0;
   G.lam1 = gw->d_lam;
   G.lam2 = gw->d_lam + B;
-  GCK(hipMemcpyAsync(gw->d_lam, lam.data(), lam.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
-  GCK(hipMemcpyAsync(gw->d_jac, jac.data(), jac.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  GCK(hipMemcpyAsync(gw->d_lam, hb.lam, 2 * (size_t)B * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  GCK(hipMemcpyAsync(gw->d_jac, hb.jac, (size_t)B * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
   GCK(hipMemcpyAsync(gw->d_prm, &P, sizeof(P), hipMemcpyHostToDevice, h->stream));
   const double* warm = nullptr;
   if (o->warm_start) {
-    if (is_device_pointer(o->warm_start)) {
-      return gfail(FLR_ERR_INVALID_ARG, "grid warm starts are host arrays (B x p)");
-    }
-    std::vector<double> wpad((size_t)B * (size_t)D.p_pad, 0.0);
-    for (int b = 0; b < B; ++b)
-      std::memcpy(&wpad[(size_t)b * D.p_pad], o->warm_start + (size_t)b * D.p, (size_t)D.p * sizeof(double));
-    GCK(hipMemcpyAsync(G.g, wpad.data(), wpad.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    GCK(hipStreamSynchronize(h->stream));
+    // B rows of p values into the padded rows of a work buffer (k_col_init reads only j < p)
+    GCK(hipMemcpy2DAsync(G.g, (size_t)D.p_pad * sizeof(double), o->warm_start, (size_t)D.p * sizeof(double),
+                         (size_t)D.p * sizeof(double), (size_t)B, hipMemcpyDefault, h->stream));
     warm = G.g;
   }
   hipLaunchKernelGGL(k_col_init, dim3((unsigned)((D.p_pad + kWG - 1) / kWG), (unsigned)B), dim3(kWG), 0, h->stream,
                      G, warm, warm ? 1 : 0, gw->d_jac);
   GCK(hipGetLastError());
-  const double one = 1.0, zero = 0.0;
   const int check_every = 8;
   // Banded columns gather their MM boundaries into every hold_period-th
   // launch while at least kHoldMinCols columns run: a boundary factors the
@@ -735,11 +704,10 @@ static flr_status grid_run(flr_problem h, const double* l1, const double* l2, in
   const int64_t max_steps =
       (int64_t)P.max_iter * ((int64_t)P.max_cg + 2 + hold_period) + 4 + 3 * check_every;
   // active columns in slot order; compacted when enough of them have finished
-  std::vector<int32_t> act((size_t)B);
-  for (int i = 0; i < B; ++i) act[(size_t)i] = i;
-  GCK(hipMemcpyAsync(gw->d_map, act.data(), act.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+  int nact = B;
+  for (int i = 0; i < B; ++i) hb.act[i] = i;
+  GCK(hipMemcpyAsync(gw->d_map, hb.act, (size_t)B * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
   GCK(hipStreamSynchronize(h->stream));
-  G.O = gw->G.O;
   double* Ospare = gw->O2;
   bool done = false;
   int64_t step = 0;
@@ -748,21 +716,18 @@ static flr_status grid_run(flr_problem h, const double* l1, const double* l2, in
   const char* prog_env = std::getenv("FLR_PROGRESS");
   const bool progress = prog_env && prog_env[0] && prog_env[0] != '0';
   auto t_prog = std::chrono::steady_clock::now();
+  auto poll = [&]() -> hipError_t {  // column states to the host: async + event, or synchronously
+    hipError_t e = hipMemcpyAsync(gw->h_st, G.st, sizeof(ColState) * (size_t)B, hipMemcpyDeviceToHost, h->stream);
+    if (e != hipSuccess) return e;
+    return gw->ev ? hipEventRecord(gw->ev, h->stream) : hipStreamSynchronize(h->stream);
+  };
   while (!done) {
     if (step >= max_steps) return gfail(FLR_ERR_DEVICE, "grid solve did not terminate within its step bound");
-    const int nact = (int)act.size();
     if (progress && std::chrono::steady_clock::now() - t_prog > std::chrono::seconds(5)) {
       t_prog = std::chrono::steady_clock::now();
       std::fprintf(stderr, "flr grid: %lld batched steps, %d of %d columns active\n", (long long)step, nact, B);
     }
-    // U = X O : column-major U (n x nact), X from its column-major copy
-    if (grid_xo(h, gw, G.O, G.U, nact) != rocblas_status_success)
-      return gfail(FLR_ERR_DEVICE, "X O product (rocblas_dgemm) failed");
-    // V = X^T U : p_pad x nact
-    if (rocblas_dgemm(gw->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)D.p_pad, nact,
-                      (rocblas_int)D.n, &one, h->X64, (rocblas_int)D.ldx, G.U, (rocblas_int)D.n, &zero, G.V,
-                      (rocblas_int)D.p_pad) != rocblas_status_success)
-      return gfail(FLR_ERR_DEVICE, "rocblas_dgemm (X^T U) failed");
+    GCK(grid_products(h, *gw, G, G.O, nact));
     const int hold = hold_period > 1 && nact >= kHoldMinCols && step % hold_period != 0 ? 1 : 0;
     if (P.band)
       hipLaunchKernelGGL(k_col<true>, dim3((unsigned)nact), dim3(kWG), 0, h->stream, G, hold);
@@ -772,50 +737,51 @@ static flr_status grid_run(flr_problem h, const double* l1, const double* l2, in
     ++step;
     if (step % check_every == 0) {
       if (pending) {
-        GCK(hipEventSynchronize(gw->ev));
+        if (gw->ev) GCK(hipEventSynchronize(gw->ev));
         int still = 0;
-        for (int i = 0; i < nact; ++i) still += gw->h_st[act[(size_t)i]].phase != PH_DONE;
+        for (int i = 0; i < nact; ++i) still += gw->h_st[hb.act[i]].phase != PH_DONE;
         if (still == 0) {
           done = true;
         } else if (nact - still >= std::max(8, nact / 8)) {
           // drain, then keep only the columns still running; their operand
           // columns move to the front of the spare buffer
+          GCK(hipMemcpyAsync(gw->h_st, G.st, sizeof(ColState) * (size_t)B, hipMemcpyDeviceToHost, h->stream));
           GCK(hipStreamSynchronize(h->stream));
-          GCK(hipMemcpy(gw->h_st, G.st, sizeof(ColState) * (size_t)B, hipMemcpyDeviceToHost));
-          std::vector<int32_t> nxt, from;
+          int cnt = 0;
           for (int i = 0; i < nact; ++i) {
-            if (gw->h_st[act[(size_t)i]].phase != PH_DONE) {
-              nxt.push_back(act[(size_t)i]);
-              from.push_back(i);
+            if (gw->h_st[hb.act[i]].phase != PH_DONE) {
+              hb.nxt[cnt] = hb.act[i];
+              hb.from[cnt] = i;
+              ++cnt;
             }
           }
-          if (nxt.empty()) {
+          if (cnt == 0) {
             done = true;
           } else {
-            GCK(hipMemcpy(gw->d_from, from.data(), from.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-            GCK(hipMemcpy(gw->d_map, nxt.data(), nxt.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-            hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((D.p_pad + kWG - 1) / kWG), (unsigned)nxt.size()),
-                               dim3(kWG), 0, h->stream, G.O, Ospare, gw->d_from, D.p_pad);
+            GCK(hipMemcpyAsync(gw->d_from, hb.from, (size_t)cnt * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+            GCK(hipMemcpyAsync(gw->d_map, hb.nxt, (size_t)cnt * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
+            hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((D.p_pad + kWG - 1) / kWG), (unsigned)cnt), dim3(kWG),
+                               0, h->stream, G.O, Ospare, gw->d_from, D.p_pad);
             GCK(hipGetLastError());
+            // the host arrays are read by the copies above before they change again
+            GCK(hipStreamSynchronize(h->stream));
             std::swap(G.O, Ospare);
-            act.swap(nxt);
+            std::swap(hb.act, hb.nxt);
+            nact = cnt;
           }
           pending = false;
           continue;
         }
       }
-      GCK(hipMemcpyAsync(gw->h_st, G.st, sizeof(ColState) * (size_t)B, hipMemcpyDeviceToHost, h->stream));
-      GCK(hipEventRecord(gw->ev, h->stream));
+      GCK(poll());
       pending = true;
     }
   }
+  GCK(hipMemcpyAsync(gw->h_st, G.st, sizeof(ColState) * (size_t)B, hipMemcpyDeviceToHost, h->stream));
+  if (beta_out)
+    GCK(hipMemcpy2DAsync(beta_out, (size_t)D.p * sizeof(double), G.x, (size_t)D.p_pad * sizeof(double),
+                         (size_t)D.p * sizeof(double), (size_t)B, hipMemcpyDefault, h->stream));
   GCK(hipStreamSynchronize(h->stream));
-  GCK(hipMemcpy(gw->h_st, G.st, sizeof(ColState) * (size_t)B, hipMemcpyDeviceToHost));
-  if (beta_out) {
-    const bool dev = is_device_pointer(beta_out);
-    GCK(hipMemcpy2D(beta_out, (size_t)D.p * sizeof(double), G.x, (size_t)D.p_pad * sizeof(double),
-                    (size_t)D.p * sizeof(double), (size_t)B, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
-  }
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   flr_status first = FLR_OK;
   for (int b = 0; b < B; ++b) {
@@ -835,48 +801,110 @@ static flr_status grid_run(flr_problem h, const double* l1, const double* l2, in
   return first;
 }
 
-extern "C" flr_status flr_solve_grid(flr_problem h, const double* l1, const double* l2, int32_t B, double tol,
-                                     const flr_solve_opts* opts, double* beta_out, flr_result* res) {
+// Argument checks shared by the grid entry points; *band: the columns with
+// lambda1 > 0 apply M^-1 through its banded factor.
+static flr_status grid_check(flr_problem h, const double* l1, const double* l2, int32_t B, double tol,
+                             const flr_solve_opts* o, bool* band) {
   if (!h || !l1 || !l2 || B < 1) return gfail(FLR_ERR_INVALID_ARG, "bad grid arguments");
   for (int32_t i = 0; i < B; ++i) {
     if (!(std::isfinite(l1[i]) && l1[i] >= 0.0) || !(std::isfinite(l2[i]) && l2[i] >= 0.0))
       return gfail(FLR_ERR_INVALID_ARG, "lambda1 and lambda2 must be finite and >= 0");
   }
   if (!(std::isfinite(tol) && tol > 0.0)) return gfail(FLR_ERR_INVALID_ARG, "tol must be finite and > 0");
+  if (o->precision != FLR_PREC_FP64) return gfail(FLR_ERR_INVALID_ARG, "grid solves run in FP64 (no mixed-precision grid path)");
+  if (!(o->eps >= 0.0) || !(o->inner_tol >= 0.0) || o->max_iter < 0 || o->max_cg < 0)
+    return gfail(FLR_ERR_INVALID_ARG, "options out of range");
+  const int pre0 = o->preconditioner;
+  if (pre0 < FLR_PRECOND_AUTO || pre0 > FLR_PRECOND_BAND) return gfail(FLR_ERR_INVALID_ARG, "unknown preconditioner");
+  if (pre0 == FLR_PRECOND_BAND && !h->band_w)
+    return gfail(FLR_ERR_INVALID_ARG, "banded preconditioner: the edge set has bandwidth < 2 or its band is too wide");
+  if (o->warm_start && is_device_pointer(o->warm_start))
+    return gfail(FLR_ERR_INVALID_ARG, "grid warm starts are host arrays (B x p)");
+  *band = h->band_w && (pre0 == FLR_PRECOND_AUTO || pre0 == FLR_PRECOND_BAND);
+  return FLR_OK;
+}
+
+extern "C" flr_status flr_solve_grid(flr_problem h, const double* l1, const double* l2, int32_t B, double tol,
+                                     const flr_solve_opts* opts, double* beta_out, flr_result* res) {
+  flr_solve_opts dflt;
+  flr_default_opts(&dflt);
+  const flr_solve_opts* o = opts ? opts : &dflt;
+  bool band = false;
+  flr_status cs = grid_check(h, l1, l2, B, tol, o, &band);
+  if (cs != FLR_OK) return cs;
   std::unique_lock<std::mutex> lk(h->busy, std::try_to_lock);
   if (!lk.owns_lock()) return gfail(FLR_ERR_BUSY, "problem handle in use by another thread");
   if (hipSetDevice(h->ctx->device) != hipSuccess) return gfail(FLR_ERR_DEVICE, "hipSetDevice failed");
-  return grid_run(h, l1, l2, B, tol, opts, beta_out, res);
+  flr_status ps = grid_prepare(h, B, band);
+  if (ps != FLR_OK) return ps;
+  std::vector<double> lam(2 * (size_t)B);
+  std::vector<int32_t> ints(4 * (size_t)B);
+  GridHost hb{lam.data(), ints.data(), ints.data() + B, ints.data() + 2 * (size_t)B, ints.data() + 3 * (size_t)B};
+  return grid_run(h, h->grid, hb, l1, l2, B, tol, o, beta_out, res);
 }
 
 extern "C" flr_status flr_profile_grid(flr_problem h, int32_t B, int32_t reps, double* avg_us) {
   if (!h || !avg_us || reps < 1 || B < 1) return gfail(FLR_ERR_INVALID_ARG, "flr_profile_grid: bad arguments");
   std::unique_lock<std::mutex> lk(h->busy, std::try_to_lock);
   if (!lk.owns_lock()) return gfail(FLR_ERR_BUSY, "problem handle in use by another thread");
-  if (!h->grid || h->grid->cap < B || !h->X64 || !h->X64c)
+  if (!h->grid || h->grid->cap < B)
     return gfail(FLR_ERR_INVALID_ARG, "flr_profile_grid: needs a completed grid solve with at least B columns");
   if (hipSetDevice(h->ctx->device) != hipSuccess) return gfail(FLR_ERR_DEVICE, "hipSetDevice failed");
   GridWork* gw = h->grid;
   const GridDev& G = gw->G;
   const Dims& D = h->D;
-  const double one = 1.0, zero = 0.0;
   hipEvent_t e[3];
   for (auto& ev : e) GCK(hipEventCreate(&ev));
-  auto gemm_u = [&]() { return grid_xo(h, gw, gw->O2, G.U, B); };
+  // the spare operand buffer, as in a batched PCG step
+  auto gemm_u = [&]() {
+    GemmArgs a{};
+    a.X = h->B.X;
+    a.ldx = D.ldx;
+    a.Bm = gw->O2;
+    a.ldb = D.p_pad;
+    a.C = gw->splitk > 1 ? gw->Upart : G.U;
+    a.ldc = G.ldu;
+    a.cslice = G.ldu * (int64_t)B;
+    a.M = (int32_t)D.n;
+    a.N = B;
+    a.K = (int32_t)(D.p_pad / gw->splitk);
+    a.tiles_m = (int32_t)((D.n + kGemmMT - 1) / kGemmMT);
+    a.tiles_n = (B + kGemmNT - 1) / kGemmNT;
+    a.nslice = gw->splitk;
+    hipError_t er = launch_gemm_xo(D.dtype, a, h->stream);
+    if (er == hipSuccess && gw->splitk > 1) {
+      const int64_t cnt = G.ldu * (int64_t)B;
+      hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((cnt + kWG - 1) / kWG)), dim3(kWG), 0, h->stream, gw->Upart,
+                         G.U, cnt, gw->splitk);
+      er = hipGetLastError();
+    }
+    return er;
+  };
   auto gemm_v = [&]() {
-    return rocblas_dgemm(gw->blas, rocblas_operation_none, rocblas_operation_none, (rocblas_int)D.p_pad, B,
-                         (rocblas_int)D.n, &one, h->X64, (rocblas_int)D.ldx, G.U, (rocblas_int)D.n, &zero, G.V,
-                         (rocblas_int)D.p_pad);
+    GemmArgs b{};
+    b.X = h->B.X;
+    b.ldx = D.ldx;
+    b.Bm = G.U;
+    b.ldb = G.ldu;
+    b.C = G.V;
+    b.ldc = D.p_pad;
+    b.M = (int32_t)D.p_pad;
+    b.N = B;
+    b.K = (int32_t)D.n;
+    b.tiles_m = (int32_t)(D.p_pad / kGemmMT);
+    b.tiles_n = (B + kGemmNT - 1) / kGemmNT;
+    b.nslice = 1;
+    return launch_gemm_xtu(D.dtype, b, h->stream);
   };
   flr_status st = FLR_OK;
   double tot[2] = {0.0, 0.0};
   for (int pass = 0; pass < 2 && st == FLR_OK; ++pass) {  // pass 0 warms up
     if (hipEventRecord(e[0], h->stream) != hipSuccess) st = FLR_ERR_DEVICE;
     for (int i = 0; i < reps && st == FLR_OK; ++i)
-      if (gemm_u() != rocblas_status_success) st = FLR_ERR_DEVICE;
+      if (gemm_u() != hipSuccess) st = FLR_ERR_DEVICE;
     if (st == FLR_OK && hipEventRecord(e[1], h->stream) != hipSuccess) st = FLR_ERR_DEVICE;
     for (int i = 0; i < reps && st == FLR_OK; ++i)
-      if (gemm_v() != rocblas_status_success) st = FLR_ERR_DEVICE;
+      if (gemm_v() != hipSuccess) st = FLR_ERR_DEVICE;
     if (st == FLR_OK && hipEventRecord(e[2], h->stream) != hipSuccess) st = FLR_ERR_DEVICE;
     if (st == FLR_OK && hipEventSynchronize(e[2]) != hipSuccess) st = FLR_ERR_DEVICE;
     float m0 = 0.f, m1 = 0.f;
@@ -892,3 +920,4 @@ extern "C" flr_status flr_profile_grid(flr_problem h, int32_t B, int32_t reps, d
   avg_us[1] = tot[1];
   return FLR_OK;
 }
+

@@ -46,9 +46,7 @@ struct flr_problem_s {
   bool has_solution = false;
   std::mutex busy;
   int64_t edges_m = 0;
-  GridWork* grid = nullptr;
-  double* X64 = nullptr;   // FP64 copy of X (row-major, as stored) for the batched X^T U (created on first use)
-  double* X64c = nullptr;  // FP64 copy of X, column-major (ld n), for the batched X O
+  GridWork* grid = nullptr;  // workspace of the last grid solve (kept while large enough)
 };
 
 
