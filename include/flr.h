@@ -148,6 +148,32 @@ flr_status flr_solve_ex(flr_problem h, double lambda1, double lambda2, double to
 flr_status flr_solve_grid(flr_problem h, const double* lambda1, const double* lambda2, int32_t B, double tol,
                           const flr_solve_opts* opts, double* beta_out, flr_result* res);
 
+/* Static workspace of flr_solve_grid_static: bytes of the per-GPU array and
+ * the most columns one call may solve. */
+#define FLR_GRID_STATIC_BYTES (64u << 20)
+#define FLR_GRID_STATIC_MAX_COLS 256
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the grid
+ * solve of flr_solve_grid - same kernels, same arithmetic, same results -
+ * with its whole device workspace (per-column vectors, batched products and
+ * their split-K partials, column states, band factors) in one static device
+ * array of FLR_GRID_STATIC_BYTES instead of memory the library allocates.
+ * The call makes no device or pinned-host allocation.  The array belongs to
+ * the loaded library: every GPU the library runs on holds it until the
+ * process ends.  All calls on one GPU share that GPU's array, which keeps the
+ * last call's contents (nothing in it has to start at zero); calls that
+ * overlap on one GPU - from different threads or different handles - race
+ * and must be serialized by the caller.  Limits: B <= FLR_GRID_STATIC_MAX_COLS
+ * and a workspace of at most FLR_GRID_STATIC_BYTES (about
+ * 8 B (13 p_pad + 9 ldu + nnz) bytes, plus 16 B p W with a banded M, where
+ * p_pad is p rounded up to the row-panel width and ldu is n rounded up to
+ * 64); beyond either it returns FLR_ERR_INVALID_ARG with the size in
+ * flr_last_error().  Arguments, outputs and other errors as flr_solve_grid;
+ * the handle's own grid workspace and footprint are not touched. */
+flr_status flr_solve_grid_static(flr_problem h, const double* lambda1, const double* lambda2, int32_t B, double tol,
+                                 const flr_solve_opts* opts, double* beta_out, flr_result* res);
+
 /* Ragged batch: `count` solves on distinct, idle problem handles of any
  * sizes and graphs (n_i, p_i, E_i), each with its own (lambda1[i],
  * lambda2[i]), in one call.  One host thread keeps two captured rotations of

@@ -30,6 +30,7 @@ EXPORTS = [
     "flr_solve_ex", "flr_solve_grid", "flr_problem_footprint", "flr_problem_n", "flr_problem_p", "flr_problem_m",
     "flr_server_create", "flr_server_submit", "flr_server_poll", "flr_server_stats", "flr_server_destroy",
     "flr_profile_kernels", "flr_profile_grid", "flr_status_string", "flr_last_error", "flr_solve_batch",
+    "flr_solve_grid_static",
 ]
 
 
@@ -73,6 +74,7 @@ def lib():
         L.flr_solve.argtypes = [vp, d, d, d, vp, C.POINTER(d), C.POINTER(i32)]
         L.flr_solve_ex.argtypes = [vp, d, d, d, C.POINTER(flr_solve_opts), vp, C.POINTER(flr_result)]
         L.flr_solve_grid.argtypes = [vp, vp, vp, i32, d, C.POINTER(flr_solve_opts), vp, vp]
+        L.flr_solve_grid_static.argtypes = [vp, vp, vp, i32, d, C.POINTER(flr_solve_opts), vp, vp]
         L.flr_problem_footprint.argtypes = [vp, C.POINTER(C.c_size_t)]
         for f in ("flr_problem_n", "flr_problem_p", "flr_problem_m"):
             getattr(L, f).argtypes = [vp]
@@ -180,6 +182,19 @@ def flr_solve_grid(h, lambda1, lambda2, tol, opts, beta_out):
     res = (flr_result * B)()
     st = lib().flr_solve_grid(h, l1.ctypes.data, l2.ctypes.data, B, tol, C.byref(opts) if opts is not None else None,
                               _ptr(beta_out), C.cast(res, C.c_void_p))
+    _check(st, ok=(FLR_OK, FLR_ERR_MAX_ITER, FLR_ERR_NUMERICAL))
+    return st, list(res)
+
+
+def flr_solve_grid_static(h, lambda1, lambda2, tol, opts, beta_out):
+    """flr_solve_grid with its workspace in the library's static device array (no allocation)."""
+    l1 = np.ascontiguousarray(lambda1, dtype=np.float64)
+    l2 = np.ascontiguousarray(lambda2, dtype=np.float64)
+    B = int(l1.size)
+    res = (flr_result * B)()
+    st = lib().flr_solve_grid_static(h, l1.ctypes.data, l2.ctypes.data, B, tol,
+                                     C.byref(opts) if opts is not None else None, _ptr(beta_out),
+                                     C.cast(res, C.c_void_p))
     _check(st, ok=(FLR_OK, FLR_ERR_MAX_ITER, FLR_ERR_NUMERICAL))
     return st, list(res)
 
@@ -325,11 +340,13 @@ class Problem:
         b = beta if isinstance(beta, np.ndarray) else beta
         return Solution(b, st, r.objective, r.mm_iters, r.cg_iters, r.rel_change, r.rel_residual, r.seconds)
 
-    def solve_grid(self, lam1, lam2, tol=1e-8, **opts):
+    def solve_grid(self, lam1, lam2, tol=1e-8, static=False, **opts):
+        """Batched grid solve; static=True uses flr_solve_grid_static (no allocation)."""
         o = default_opts(**opts)
         B = len(lam1)
         beta = np.zeros((B, self.p))
-        st, res = flr_solve_grid(self.h, lam1, lam2, tol, o, beta)
+        fn = flr_solve_grid_static if static else flr_solve_grid
+        st, res = fn(self.h, lam1, lam2, tol, o, beta)
         return st, beta, [r.as_dict() for r in res]
 
     def close(self):

@@ -921,3 +921,80 @@ extern "C" flr_status flr_profile_grid(flr_problem h, int32_t B, int32_t reps, d
   return FLR_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// No-allocation grid solve: the workspace is a fixed static device array
+// (scratch) instead of memory the library allocates.  In host code the name
+// `scratch` is only a stand-in for the symbol; its device address comes from
+// hipGetSymbolAddress, once per device, and only that address is used.
+// ---------------------------------------------------------------------------
+static constexpr size_t kGridScratchBytes = (size_t)FLR_GRID_STATIC_BYTES;
+static constexpr int kGridStaticMaxCols = FLR_GRID_STATIC_MAX_COLS;
+static __device__ __align__(256) char scratch[kGridScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (looked up on first use with
+// the device current).
+flr_status scratch_address(int device, char** out) {
+  if (device < 0 || device >= kMaxDevices) return gfail(FLR_ERR_DEVICE, "device id beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return gfail(FLR_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = static_cast<char*>(ptr);
+  }
+  *out = g_scratch_ptr[device];
+  return FLR_OK;
+}
+}  // namespace
+
+extern "C" flr_status flr_solve_grid_static(flr_problem h, const double* l1, const double* l2, int32_t B, double tol,
+                                            const flr_solve_opts* opts, double* beta_out, flr_result* res) {
+  flr_solve_opts dflt;
+  flr_default_opts(&dflt);
+  const flr_solve_opts* o = opts ? opts : &dflt;
+  bool band = false;
+  flr_status cs = grid_check(h, l1, l2, B, tol, o, &band);
+  if (cs != FLR_OK) return cs;
+  if (B > kGridStaticMaxCols)
+    return gfail(FLR_ERR_INVALID_ARG, "flr_solve_grid_static: at most " + std::to_string(kGridStaticMaxCols) +
+                                          " columns per call");
+  std::unique_lock<std::mutex> lk(h->busy, std::try_to_lock);
+  if (!lk.owns_lock()) return gfail(FLR_ERR_BUSY, "problem handle in use by another thread");
+  if (hipSetDevice(h->ctx->device) != hipSuccess) return gfail(FLR_ERR_DEVICE, "hipSetDevice failed");
+  GridWork gw;
+  gw.cap = B;
+  gw.band = band;
+  GridCarve c;
+  grid_carve(c, gw, h->D, B, h->nnz, h->band_w, band);
+  if (c.used > kGridScratchBytes)
+    return gfail(FLR_ERR_INVALID_ARG, "flr_solve_grid_static: the workspace needs " + std::to_string(c.used) +
+                                          " bytes, more than the " + std::to_string(kGridScratchBytes) +
+                                          "-byte static array (fewer columns, or flr_solve_grid)");
+  char* base = nullptr;
+  flr_status ss = scratch_address(h->ctx->device, &base);
+  if (ss != FLR_OK) return ss;
+  c.base = base;
+  c.used = 0;
+  grid_carve(c, gw, h->D, B, h->nnz, h->band_w, band);
+  grid_bind(gw, h);
+  gw.block = base;
+  gw.bytes = c.used;
+  gw.owned = false;
+  // host arrays without allocation: per-thread static storage
+  static thread_local ColState st_host[kGridStaticMaxCols];
+  static thread_local double lam_host[2 * kGridStaticMaxCols];
+  static thread_local int32_t int_host[4 * kGridStaticMaxCols];
+  gw.h_st = st_host;
+  gw.ev = nullptr;
+  GridHost hb{lam_host, int_host, int_host + B, int_host + 2 * B, int_host + 3 * B};
+  const flr_status st = grid_run(h, &gw, hb, l1, l2, B, tol, o, beta_out, res);
+  gw.h_st = nullptr;  // static storage: nothing to free
+  return st;
+}
