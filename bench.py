@@ -72,15 +72,21 @@ def make_workload(name):
 
 
 def cpu_baseline(inst, gpu_cg_total: int, mm_sample: int):
-    """The FP64 oracle (Algorithm 2, as it stands) on a bounded sample of the
-    same solve: the first mm_sample MM iterations.  Extrapolated to a full
-    solve by the PCG step count of the GPU solve of the same instance."""
+    """The FP64 oracle (Algorithm 2, as it stands) on the same instance, on the
+    host's cores.  mm_sample > 0: a bounded sample, the first mm_sample MM
+    iterations, scaled to a whole solve by PCG steps (every PCG step of the
+    oracle costs the same: two products with X, the Laplacian and two banded
+    sweeps); mm_sample = 0: one complete solve, timed."""
     import oracle
 
     P = oracle.Problem.from_instance(inst)
     t0 = time.perf_counter()
     r = oracle.solve(P, inst.lam1, inst.lam2, eps=inst.eps, tol=inst.tol, max_iter=mm_sample, method=oracle.ALG2)
     dt = time.perf_counter() - t0
+    if mm_sample <= 0:
+        return {"value": 1.0 / dt, "unit": "solves/s", "cores": int(r.threads), "kind": "oracle",
+                "sample": "one complete solve (%d MM iterations, %d PCG steps) in %.1f s on %d threads" % (
+                    r.mm_iters, r.cg_iters, dt, r.threads)}
     cg = max(1, r.cg_iters)
     sec_per_solve = dt / cg * max(gpu_cg_total, 1)
     return {
@@ -88,8 +94,8 @@ def cpu_baseline(inst, gpu_cg_total: int, mm_sample: int):
         "unit": "solves/s",
         "cores": int(r.threads),
         "kind": "oracle",
-        "sample": "first %d MM iterations (%d PCG steps, %.1f s incl. setup) of the same solve on %d threads; "
-                  "scaled by the full solve's %d PCG steps" % (mm_sample, r.cg_iters, dt, r.threads, gpu_cg_total),
+        "sample": "first %d MM iterations of the same solve (%d PCG steps, %.1f s) on %d threads, scaled by "
+                  "PCG steps to the whole solve's %d" % (r.mm_iters, r.cg_iters, dt, r.threads, gpu_cg_total),
     }
 
 
@@ -101,7 +107,9 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-mm-sample", type=int, default=4)
+    ap.add_argument("--cpu-mm-sample", type=int, default=60,
+                    help="oracle baseline: MM iterations sampled (about 20 s on 16 host threads for c2)")
+    ap.add_argument("--cpu-full", action="store_true", help="oracle baseline: one complete solve instead")
     ap.add_argument("--profile-reps", type=int, default=200)
     ap.add_argument("--mm-cap", type=int, default=0, help="cap on MM iterations (profiling runs only)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -169,8 +177,9 @@ def main():
     dom_name, dom_us = ("gemv_a", a_us) if a_us >= b_us else ("gemv_b", b_us)
     achieved = alg_bytes / (dom_us * 1e-6) / 1e9
     traffic = measured_traffic(dom_name, wname)
-    # effective bandwidth of the whole solve: two X passes per PCG step, three per MM iteration
-    passes = 2 * s.cg_iters + 3 * s.mm_iters
+    # algorithmic bandwidth of the whole solve: two X passes per PCG step (X p, then X^T u) and two per
+    # MM boundary (X beta, X^T X beta), over the wall time of a solve
+    passes = 2 * s.cg_iters + 2 * s.mm_iters
     solve_gbs = passes * inst.n * inst.p * xbytes / (elapsed / args.steps) / 1e9
 
     line = {
@@ -192,12 +201,14 @@ def main():
                    "objective": s.objective, "solve_effective_GBps": solve_gbs},
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "avg_us": dom_us,
+                     "avg_us_how": "HIP events around %d back-to-back launches in the PCG-step state on the "
+                                   "problem's stream" % args.profile_reps,
                      "algorithmic_bytes": alg_bytes, "other_kernel_us": b_us if dom_name == "gemv_a" else a_us,
-                     "block_kernel_us": c_us},
+                     "block_kernel_us": c_us, "solve_achieved": solve_gbs, "solve_frac": solve_gbs / HBM_PEAK_GBS},
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(inst, s.cg_iters, args.cpu_mm_sample)
+        line["cpu_baseline"] = cpu_baseline(inst, s.cg_iters, 0 if args.cpu_full else args.cpu_mm_sample)
     if args.calibrate_copy:
         nb = args.calibrate_copy * (1 << 20)
         src = torch.ones(nb // 4, dtype=torch.float32, device="cuda:0")

@@ -182,13 +182,17 @@ def ar1_x(n: int, p: int, rho: float, rng: np.random.Generator, dtype: int) -> n
     return store(x, dtype)
 
 
-def matvec_rows(xs: np.ndarray, dtype: int, v: np.ndarray, chunk_rows: int = 1024) -> np.ndarray:
-    """FP64 X v for the data model y = X beta + noise (chunked widening)."""
+def matvec_rows(xs: np.ndarray, dtype: int, v: np.ndarray, chunk_rows: int = 256) -> np.ndarray:
+    """FP64 X v for the data model y = X beta + noise (chunked widening).
+
+    Each row is summed by numpy's own pairwise reduction rather than a BLAS
+    product, whose summation order depends on its thread count: the same
+    seed must give bitwise the same y on every machine."""
     n = xs.shape[0]
     out = np.empty(n)
     for r0 in range(0, n, chunk_rows):
         r1 = min(n, r0 + chunk_rows)
-        out[r0:r1] = widen(xs[r0:r1], dtype) @ v
+        out[r0:r1] = np.add.reduce(widen(xs[r0:r1], dtype) * v[None, :], axis=1)
     return out
 
 

@@ -148,6 +148,23 @@ flr_status flr_solve_ex(flr_problem h, double lambda1, double lambda2, double to
 flr_status flr_solve_grid(flr_problem h, const double* lambda1, const double* lambda2, int32_t B, double tol,
                           const flr_solve_opts* opts, double* beta_out, flr_result* res);
 
+/* Warm-started sequence of solves on one problem: a regularization path over
+ * (lambda1[k], lambda2[k]) and/or eps-continuation over eps[k] (section 3.2:
+ * minimizers of the perturbed objective approach a minimizer of f as eps
+ * decreases to 0, Lemma 1; section 5 fixes eps but notes that it could be
+ * decreased).  Point k is solved as flr_solve_ex with its own lambdas and
+ * eps, warm-started at point k-1's solution; point 0 starts from
+ * opts->warm_start, or the initialization of Algorithms 1 and 2 when NULL.
+ * eps: host, count values (> 0), or NULL for opts->eps at every point.
+ * lambda1, lambda2: host, count values.  beta_out: nullable, host or device,
+ * count x p row-major; res: nullable, count entries.  Stops at the first
+ * point that fails validation or the device (its status is returned); points
+ * that end in FLR_ERR_MAX_ITER / FLR_ERR_NUMERICAL are reported in res and
+ * the path goes on from their last iterate.  Returns FLR_OK when every point
+ * converged, else the first failing point's status. */
+flr_status flr_solve_path(flr_problem h, const double* lambda1, const double* lambda2, const double* eps, int32_t count,
+                          double tol, const flr_solve_opts* opts, double* beta_out, flr_result* res);
+
 /* Static workspace of flr_solve_grid_static: bytes of the per-GPU array and
  * the most columns one call may solve. */
 #define FLR_GRID_STATIC_BYTES (64u << 20)

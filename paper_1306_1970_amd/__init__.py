@@ -30,7 +30,7 @@ EXPORTS = [
     "flr_solve_ex", "flr_solve_grid", "flr_problem_footprint", "flr_problem_n", "flr_problem_p", "flr_problem_m",
     "flr_server_create", "flr_server_submit", "flr_server_poll", "flr_server_stats", "flr_server_destroy",
     "flr_profile_kernels", "flr_profile_grid", "flr_status_string", "flr_last_error", "flr_solve_batch",
-    "flr_solve_grid_static",
+    "flr_solve_grid_static", "flr_solve_path",
 ]
 
 
@@ -75,6 +75,7 @@ def lib():
         L.flr_solve_ex.argtypes = [vp, d, d, d, C.POINTER(flr_solve_opts), vp, C.POINTER(flr_result)]
         L.flr_solve_grid.argtypes = [vp, vp, vp, i32, d, C.POINTER(flr_solve_opts), vp, vp]
         L.flr_solve_grid_static.argtypes = [vp, vp, vp, i32, d, C.POINTER(flr_solve_opts), vp, vp]
+        L.flr_solve_path.argtypes = [vp, vp, vp, vp, i32, d, C.POINTER(flr_solve_opts), vp, vp]
         L.flr_problem_footprint.argtypes = [vp, C.POINTER(C.c_size_t)]
         for f in ("flr_problem_n", "flr_problem_p", "flr_problem_m"):
             getattr(L, f).argtypes = [vp]
@@ -195,6 +196,19 @@ def flr_solve_grid_static(h, lambda1, lambda2, tol, opts, beta_out):
     st = lib().flr_solve_grid_static(h, l1.ctypes.data, l2.ctypes.data, B, tol,
                                      C.byref(opts) if opts is not None else None, _ptr(beta_out),
                                      C.cast(res, C.c_void_p))
+    _check(st, ok=(FLR_OK, FLR_ERR_MAX_ITER, FLR_ERR_NUMERICAL))
+    return st, list(res)
+
+
+def flr_solve_path(h, lambda1, lambda2, eps, tol, opts, beta_out):
+    """Warm-started sequence of solves (regularization path and/or eps-continuation)."""
+    l1 = np.ascontiguousarray(lambda1, dtype=np.float64)
+    l2 = np.ascontiguousarray(lambda2, dtype=np.float64)
+    e = None if eps is None else np.ascontiguousarray(eps, dtype=np.float64)
+    k = int(l1.size)
+    res = (flr_result * k)()
+    st = lib().flr_solve_path(h, l1.ctypes.data, l2.ctypes.data, None if e is None else e.ctypes.data, k, tol,
+                              C.byref(opts) if opts is not None else None, _ptr(beta_out), C.cast(res, C.c_void_p))
     _check(st, ok=(FLR_OK, FLR_ERR_MAX_ITER, FLR_ERR_NUMERICAL))
     return st, list(res)
 
@@ -347,6 +361,13 @@ class Problem:
         beta = np.zeros((B, self.p))
         fn = flr_solve_grid_static if static else flr_solve_grid
         st, res = fn(self.h, lam1, lam2, tol, o, beta)
+        return st, beta, [r.as_dict() for r in res]
+
+    def solve_path(self, lam1, lam2, tol=1e-8, eps=None, **opts):
+        """Solves along (lam1[k], lam2[k], eps[k]), each warm-started at the previous solution."""
+        o = default_opts(**opts)
+        beta = np.zeros((len(lam1), self.p))
+        st, res = flr_solve_path(self.h, lam1, lam2, eps, tol, o, beta)
         return st, beta, [r.as_dict() for r in res]
 
     def close(self):

@@ -189,7 +189,10 @@ flr_status solve_begin(flr_problem h, double l1, double l2, double tol, const fl
   flr_status gs = build_graph(h, mixed, band);
   if (gs != FLR_OK) return gs;
   run.gexec = h->gexec[mixed][band];
-  run.max_launches = ((int64_t)P.max_iter * ((int64_t)P.max_cg + 2) + 2) / kRounds + 4;
+  // every MM step takes at most max_cg PCG steps, as many FP64 residual
+  // refreshes (mixed precision: each follows at least one PCG step) and its
+  // boundary; one graph launch holds kRounds rotations
+  run.max_launches = ((int64_t)P.max_iter * (2 * (int64_t)P.max_cg + 2) + 2) / kRounds + 4;
   run.launched = 0;
   run.in_flight = 0;
   run.done = false;
@@ -614,6 +617,38 @@ flr_status flr_solve_batch(const flr_problem* hs, int32_t count, const double* l
   flr_status first = FLR_OK;
   for (int32_t i = 0; i < count; ++i) {
     flr_status st = solve_end(runs[(size_t)i], beta_out ? beta_out[i] : nullptr, res ? &res[i] : nullptr);
+    if (st != FLR_OK && first == FLR_OK) first = st;
+  }
+  return first;
+}
+
+flr_status flr_solve_path(flr_problem h, const double* l1, const double* l2, const double* eps, int32_t count,
+                          double tol, const flr_solve_opts* opts, double* beta_out, flr_result* res) {
+  if (!h || !l1 || !l2 || count < 1) return fail(FLR_ERR_INVALID_ARG, "flr_solve_path: bad arguments");
+  for (int32_t k = 0; k < count; ++k) {
+    flr_status v = validate_lambdas(l1[k], l2[k], tol);
+    if (v != FLR_OK) return v;
+    if (eps && !(std::isfinite(eps[k]) && eps[k] > 0.0))
+      return fail(FLR_ERR_INVALID_ARG, "flr_solve_path: every eps must be finite and > 0");
+  }
+  std::unique_lock<std::mutex> lk(h->busy, std::try_to_lock);
+  if (!lk.owns_lock()) return fail(FLR_ERR_BUSY, "problem handle in use by another thread");
+  if (hipSetDevice(h->ctx->device) != hipSuccess) return fail(FLR_ERR_DEVICE, "hipSetDevice failed");
+  flr_solve_opts o;
+  flr_default_opts(&o);
+  if (opts) o = *opts;
+  flr_status first = FLR_OK;
+  for (int32_t k = 0; k < count; ++k) {
+    if (eps) o.eps = eps[k];
+    if (k > 0) {  // warm start at the previous point's solution (kept on the handle)
+      o.warm_start = nullptr;
+      o.use_last = 1;
+    }
+    double* bk = beta_out ? beta_out + (size_t)k * (size_t)h->D.p : nullptr;
+    flr_result r{};
+    flr_status st = run_solve(h, l1[k], l2[k], tol, &o, bk, &r);
+    if (st != FLR_OK && st != FLR_ERR_MAX_ITER && st != FLR_ERR_NUMERICAL) return st;
+    if (res) res[k] = r;
     if (st != FLR_OK && first == FLR_OK) first = st;
   }
   return first;

@@ -27,7 +27,16 @@ constexpr int kMaxBlocks = 1024;  // max solver blocks -> p_pad <= 262144
 
 // PH_BANDMM: an MM step goes on and M is banded (bandwidth >= 2): the fourth
 // launch of the rotation factors M and solves with the new residual.
-enum Phase : int32_t { PH_CG = 0, PH_END = 1, PH_DONE = 2, PH_BANDMM = 3 };
+// PH_RES (mixed precision): the inner PCG with FP32 products has met its
+// tolerance on its recursive residual; the next rotation recomputes the true
+// residual c - Q x in FP64 at the same weights and either ends the MM step
+// or restarts the PCG from it (iterative refinement).  PH_BANDRES: the same
+// refreshed residual solved through the existing banded factor.
+enum Phase : int32_t { PH_CG = 0, PH_END = 1, PH_DONE = 2, PH_BANDMM = 3, PH_RES = 4, PH_BANDRES = 5 };
+
+// What a combine of the block scalars follows: a PCG step, the first residual
+// of an MM step, or a residual refreshed in FP64 (refinement).
+enum CombineMode : int32_t { CM_STEP = 0, CM_FIRST = 1, CM_REFRESH = 2 };
 enum SolveStatus : int32_t { ST_OK = 0, ST_MAX_ITER = 1, ST_NUMERICAL = 2 };
 
 // Block scalars of the partitioned tridiagonal solve (index into blk[]).
@@ -55,7 +64,8 @@ struct State {
   int32_t phase, status, first, first_cg;
   int32_t mm_iter, cg_iter;
   int64_t cg_total;
-  double rz, f_old, f_new, rel_change, rel_res, nu, gamma, pad;
+  double rz, f_old, f_new, rel_change, rel_res, nu, gamma;
+  double rres;  // relative FP64 residual at the last MM boundary or refresh (mixed precision)
 };
 
 struct Dims {

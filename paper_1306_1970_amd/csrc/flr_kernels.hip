@@ -97,6 +97,8 @@ __global__ __launch_bounds__(kWG) void k_init(Dims D, Bufs B, const double* __re
     s.rel_change = 0.0;
     s.rel_res = 0.0;
     s.nu = 0.0;
+    s.gamma = 0.0;
+    s.rres = 0.0;
     B.st[0] = s;
     B.st[1] = s;
   }
@@ -334,7 +336,7 @@ __global__ __launch_bounds__(kWG) void k_gemv_b(Dims D, Bufs B, const State* __r
         for (int q = 0; q < D.cb1; ++q) u += B.upart[(int64_t)q * D.n + r0 + t];
       }
       sh_u[t] = u;
-      if (!cg && cb == 0) {
+      if (!cg && cb == 0) {  // loss partials (used at an MM boundary)
         const double dlt = B.y[r0 + t] - u;
         loss = fma(dlt, dlt, loss);
       }
@@ -364,7 +366,8 @@ __global__ __launch_bounds__(kWG) void k_gemv_b(Dims D, Bufs B, const State* __r
     if (tid == 0) B.pqpart[wg] = 0.0;
   }
 
-  if (!cg && wg < D.nblk) {
+  const bool mmb = s.phase == PH_END;  // an MM boundary (not a refinement's residual refresh)
+  if (mmb && wg < D.nblk) {
     // reweighting and the tridiagonal part of M, penalties
     const int64_t j = (int64_t)wg * kBlk + tid;
     double pen = 0.0, dj = 1.0, ej = 0.0;
@@ -395,7 +398,7 @@ __global__ __launch_bounds__(kWG) void k_gemv_b(Dims D, Bufs B, const State* __r
     const double tot = wg_sum(pen, sh_s);
     if (tid == 0) B.penpart[wg] = tot;
   }
-  if (!cg) {
+  if (mmb) {
     // The last workgroup to finish factors M = L D L^T over all p elements
     // (one wave runs the pivot chain); writes L and 1/D for the C launch.
     __shared__ int sh_flag;
@@ -444,10 +447,44 @@ __device__ inline void block_local_solve(const Dims& D, const Bufs& B, int b, in
   }
 }
 
+// Reduction of the true residual that one refinement round asks of the
+// FP32-product PCG (its products carry errors near 1e-7 relative, so it
+// cannot be trusted much further in one round).
+constexpr double kRoundReduction = 1e-4;
+
+// Phase after a new residual (its squared norm rr, relative norm rn); also
+// records the FP64 residual of a boundary or refresh in o.rres.
+// Algorithm 2's inner loop is repeat-until: after the first residual of an
+// MM step at least one PCG step runs unless that residual is exactly zero (nu
+// would be 0/0).  After a PCG step the inner test decides.  With FP32
+// products (mixed precision) a round of PCG stops once its recursive residual
+// is kRoundReduction below the round's FP64 starting residual (or meets the
+// inner tolerance); then the true residual c - Q x is recomputed in FP64 and
+// the MM step ends only if that passes the inner test - else PCG restarts
+// from it (iterative refinement).  Refinement also ends when a refresh has
+// cut the true residual by less than 10 % (FP32 products can resolve no more
+// on this system) or at the PCG step cap.
+__device__ inline int32_t next_phase(const Params& prm, State& o, int mode, double rr, double rn) {
+  const bool capped = o.cg_iter >= prm.max_cg;
+  if (mode == CM_FIRST) {
+    o.rres = rn;
+    return rr > 0.0 ? PH_CG : PH_END;
+  }
+  const bool met = !(rn > prm.inner_tol);
+  if (mode == CM_REFRESH) {
+    const bool stalled = !(rn < 0.9 * o.rres);
+    o.rres = rn;
+    return (met || capped || stalled) ? PH_END : PH_CG;
+  }
+  if (capped) return PH_END;
+  if (!prm.mixed) return met ? PH_END : PH_CG;
+  return (met || !(rn > kRoundReduction * o.rres)) ? PH_RES : PH_CG;
+}
+
 // Wave-level variant of combine_blocks for K <= 256 (4 blocks per lane),
 // run by wave 0 alone: shuffles only, no barriers.
 __device__ void combine_blocks_wave(const Dims& D, const Bufs& B, const Params& prm, State o, double rz_prev,
-                                    bool first_step, State* __restrict__ sout) {
+                                    int mode, State* __restrict__ sout) {
   constexpr int E = 4;
   const int l = threadIdx.x & 63;
   const int K = D.nblk;
@@ -514,13 +551,10 @@ __device__ void combine_blocks_wave(const Dims& D, const Bufs& B, const Params& 
   const double rr = wave_sum(rrp);
   if (l == 0) {
     const double rn = sqrt(rr) / prm.cnorm;
-    // Algorithm 2's inner loop is repeat-until: after r0 (first_step) at least
-    // one PCG step runs unless r0 is exactly zero (nu would be 0/0)
-    const bool done = first_step ? !(rr > 0.0) : (!(rn > prm.inner_tol) || o.cg_iter >= prm.max_cg);
+    o.phase = next_phase(prm, o, mode, rr, rn);
     o.rel_res = rn;
     o.rz = rz;
-    o.gamma = first_step ? 0.0 : rz / rz_prev;
-    o.phase = done ? PH_END : PH_CG;
+    o.gamma = mode != CM_STEP ? 0.0 : rz / rz_prev;
     *sout = o;
     *B.counter = 0u;
   }
@@ -532,7 +566,7 @@ __device__ void combine_blocks_wave(const Dims& D, const Bufs& B, const Params& 
 // backward Z_k = solution value entering block k from the right), r^T z,
 // ||r||, the inner stopping test of Algorithm 2 and gamma = r^T z / r_old^T z_old.
 __device__ void combine_blocks(const Dims& D, const Bufs& B, const Params& prm, State o, double rz_prev,
-                               bool first_step, State* __restrict__ sout, double* sh_m, double* sh_G, double* sh_Z) {
+                               int mode, State* __restrict__ sout, double* sh_m, double* sh_G, double* sh_Z) {
   constexpr int EMAX = kMaxBlocks / kWG;
   const int tid = threadIdx.x;
   const int K = D.nblk;
@@ -605,13 +639,10 @@ __device__ void combine_blocks(const Dims& D, const Bufs& B, const Params& prm, 
   const double rr = wg_sum(rrp, sh_m + 8);
   if (tid == 0) {
     const double rn = sqrt(rr) / prm.cnorm;
-    // Algorithm 2's inner loop is repeat-until: after r0 (first_step) at least
-    // one PCG step runs unless r0 is exactly zero (nu would be 0/0)
-    const bool done = first_step ? !(rr > 0.0) : (!(rn > prm.inner_tol) || o.cg_iter >= prm.max_cg);
+    o.phase = next_phase(prm, o, mode, rr, rn);
     o.rel_res = rn;
     o.rz = rz;
-    o.gamma = first_step ? 0.0 : rz / rz_prev;
-    o.phase = done ? PH_END : PH_CG;
+    o.gamma = mode != CM_STEP ? 0.0 : rz / rz_prev;
     *sout = o;
     *B.counter = 0u;
   }
@@ -725,15 +756,15 @@ __global__ __launch_bounds__(kWG) void k_block(Dims D, Bufs B, const State* __re
       o.cg_total = s.cg_total + 1;
       o.nu = nu;
       if (D.nblk <= 4 * 64) {
-        if (tid < 64) combine_blocks_wave(D, B, prm, o, s.rz, false, sout);
+        if (tid < 64) combine_blocks_wave(D, B, prm, o, s.rz, CM_STEP, sout);
       } else {
-        combine_blocks(D, B, prm, o, s.rz, false, sout, lds, sh_G, sh_Z);
+        combine_blocks(D, B, prm, o, s.rz, CM_STEP, sout, lds, sh_G, sh_Z);
       }
     }
     return;
   }
 
-  // ---- MM boundary ----
+  // ---- MM boundary, or an FP64 residual refresh (refinement) ----
   // inputs that do not depend on the decision, loaded up front (L and 1/D come
   // from the sequential factorization at the end of the B launch)
   double cj = 0.0, qsum = 0.0, Lj = 0.0, invDj = 0.0, Lnb = 0.0;
@@ -744,6 +775,36 @@ __global__ __launch_bounds__(kWG) void k_block(Dims D, Bufs B, const State* __re
     for (int rb = 0; rb < D.rb2; ++rb) qsum += B.qpart[(int64_t)rb * D.p_pad + j];
   }
   if (tid == 0) Lnb = (j + kBlk < D.p) ? B.L[j + kBlk] : 0.0;
+  if (s.phase == PH_RES) {
+    // true residual c - (X^T X + M) x of this MM step's system, in FP64 (the
+    // weights and the factorization of M are the ones the PCG used)
+    double rj = 0.0;
+    if (real) {
+      rj = cj - (qsum + apply_m(B, prm, j, B.x));
+      B.r[j] = rj;
+    }
+    if (prm.band) {  // the K launch solves with the existing factor
+      if (b == 0 && tid == 0) {
+        State o = s;
+        o.phase = PH_BANDRES;
+        *sout = o;
+      }
+      return;
+    }
+    const double sigj = real ? B.sig[j] : 0.0, psij = real ? B.psi[j] : 0.0;
+    sh_L[tid] = Lj;
+    if (tid == 0) sh_L[kBlk] = Lnb;
+    __syncthreads();
+    block_local_solve(D, B, b, j, rj, Lj, sh_L[tid + 1], invDj, sigj, psij, lds, lds2);
+    if (arrive_last(B, D.nblk, &sh_flag)) {
+      if (D.nblk <= 4 * 64) {
+        if (tid < 64) combine_blocks_wave(D, B, prm, s, 0.0, CM_REFRESH, sout);
+      } else {
+        combine_blocks(D, B, prm, s, 0.0, CM_REFRESH, sout, lds, sh_G, sh_Z);
+      }
+    }
+    return;
+  }
   // f(b) = loss + penalties (identical arithmetic in every workgroup)
   double fpart = 0.0;
   for (int q = tid; q < D.rb2; q += kWG) fpart += B.losspart[q];
@@ -824,9 +885,9 @@ __global__ __launch_bounds__(kWG) void k_block(Dims D, Bufs B, const State* __re
   block_local_solve(D, B, b, j, rj, Lj, Lnext, invDj, sigj, psij, lds, lds2);
   if (arrive_last(B, D.nblk, &sh_flag)) {
     if (D.nblk <= 4 * 64) {
-      if (tid < 64) combine_blocks_wave(D, B, prm, o, 0.0, true, sout);
+      if (tid < 64) combine_blocks_wave(D, B, prm, o, 0.0, CM_FIRST, sout);
     } else {
-      combine_blocks(D, B, prm, o, 0.0, true, sout, lds, sh_G, sh_Z);
+      combine_blocks(D, B, prm, o, 0.0, CM_FIRST, sout, lds, sh_G, sh_Z);
     }
   }
 }
@@ -843,7 +904,7 @@ __global__ __launch_bounds__(kWG) void k_band(Dims D, Bufs B, const State* __res
   __shared__ double red[24];
   const State s = *sin;
   const int tid = threadIdx.x;
-  if (s.phase == PH_DONE || s.phase == PH_END) {  // nothing to solve (finished, or not banded mode)
+  if (s.phase != PH_CG && s.phase != PH_BANDMM && s.phase != PH_BANDRES) {  // nothing to solve
     if (tid == 0) *sout = s;
     return;
   }
@@ -874,12 +935,11 @@ __global__ __launch_bounds__(kWG) void k_band(Dims D, Bufs B, const State* __res
   wg_sum4(sums, red);
   if (tid == 0) {
     const double rz = sums[0], rn = sqrt(sums[1]) / prm.cnorm;
-    // repeat-until: after r0 at least one PCG step, unless r0 is exactly zero
-    const bool done = mm ? !(sums[1] > 0.0) : (!(rn > prm.inner_tol) || o.cg_iter >= prm.max_cg);
+    const int mode = mm ? CM_FIRST : s.phase == PH_BANDRES ? CM_REFRESH : CM_STEP;
+    o.phase = next_phase(prm, o, mode, sums[1], rn);
     o.rel_res = rn;
-    o.gamma = mm ? 0.0 : rz / s.rz;
+    o.gamma = mode != CM_STEP ? 0.0 : rz / s.rz;
     o.rz = rz;
-    o.phase = done ? PH_END : PH_CG;
     *sout = o;
   }
 }

@@ -1,6 +1,9 @@
 """Batched (lambda1, lambda2) grid solves: every column against the FP64
 oracle (same bar as the single-solve parity tests) and against the single
 solve of the same column."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -36,18 +39,30 @@ def _grid(flr, ctx, inst, l1, l2, tol, **kw):
     return st, beta, res, singles
 
 
-# Bars per instance: beta 1e-8 and objective 1e-11 where the MM trajectory at tol 1e-7 is insensitive to
-# rounding.  On the p = 2500 and p = 4100 instances the columns with lambda1 = 0.05 are not: the oracle's
-# own answer moves by up to 3.3e-7 in beta and 9e-11 in the objective when y is perturbed by one ulp, and
-# by 8.8e-7 / 4.1e-10 between its Algorithm 1 and Algorithm 2 (same MM count).  Products summed in a
-# different order perturb every PCG step, so those instances take 5e-6 (beta) and 1e-9 (objective).
-@pytest.mark.parametrize("n,p,dtype,beta_bar,obj_bar", [(80, 600, flrgen.F64, 1e-8, 1e-11),
-                                                        (120, 2500, flrgen.F32, 5e-6, 1e-9),
-                                                        (60, 4100, flrgen.BF16, 5e-6, 1e-9)])
-def test_grid_chain_matches_oracle(flr, ctx, n, p, dtype, beta_bar, obj_bar):
+# Bars per column from the oracle's own rounding spread (tests/golden/grid_oracle_spread.json, written by
+# make_grid_spread.py from the oracle alone): the oracle run with the columns of X in reverse order (every
+# product summed in another order) and with y moved by one ulp.  Where the MM trajectory is insensitive the
+# spread is below 1e-10 and the bar is the FP64 parity bar (beta 1e-8, objective 1e-11); on the few columns
+# whose trajectory amplifies rounding (lambda1 = 0.05: weights 1/(|b| + eps) on coordinates near zero) no
+# implementation can do better than that spread, and the bar is twice it.
+with open(os.path.join(os.path.dirname(__file__), "golden", "grid_oracle_spread.json")) as _fh:
+    SPREAD = json.load(_fh)
+
+
+def _bars(n, p, dtype):
+    for inst in SPREAD["instances"]:
+        if (inst["n"], inst["p"], inst["dtype"]) == (n, p, dtype):
+            return [(max(1e-8, 2.0 * c["beta_spread"]), max(1e-11, 2.0 * c["objective_spread"]))
+                    for c in inst["columns"]]
+    raise KeyError((n, p, dtype))
+
+
+@pytest.mark.parametrize("n,p,dtype", [(80, 600, flrgen.F64), (120, 2500, flrgen.F32), (60, 4100, flrgen.BF16)])
+def test_grid_chain_matches_oracle(flr, ctx, n, p, dtype):
     inst = flrgen.small_instance(n, p, "chain", dtype=dtype, seed=31)
     vals = np.array([0.05, 0.4, 1.5])
     l1, l2 = flrgen.grid_lambdas(vals)
+    bars = _bars(n, p, dtype)
     print("grid %s B=%d" % (inst.name, l1.size), flush=True)
     # inner cap raised so that every inner solve really reaches 1e-12 (a capped, inexact
     # inner solve makes the MM trajectory depend on rounding detail)
@@ -56,14 +71,17 @@ def test_grid_chain_matches_oracle(flr, ctx, n, p, dtype, beta_bar, obj_bar):
     for b in range(l1.size):
         ref = oracle.solve(P, l1[b], l2[b], tol=1e-7, inner_tol=INNER, method=oracle.ALG2, max_cg=20 * inst.p)
         err = np.max(np.abs(beta[b] - ref.beta)) / np.max(np.abs(ref.beta))
-        print("  col %d lam=(%g,%g) grid mm=%d cg=%d | oracle mm=%d | single mm=%d | err=%.2e" %
-              (b, l1[b], l2[b], res[b]["mm_iters"], res[b]["cg_iters"], ref.mm_iters, singles[b].mm_iters, err),
-              flush=True)
+        err_single = np.max(np.abs(beta[b] - singles[b].beta)) / np.max(np.abs(singles[b].beta))
+        ebar, obar = bars[b]
+        print("  col %d lam=(%g,%g) grid mm=%d cg=%d | oracle mm=%d | single mm=%d | err=%.2e (bar %.1e) "
+              "vs single %.2e" % (b, l1[b], l2[b], res[b]["mm_iters"], res[b]["cg_iters"], ref.mm_iters,
+                                  singles[b].mm_iters, err, ebar, err_single), flush=True)
         assert res[b]["status"] == flr.FLR_OK
         assert res[b]["mm_iters"] == ref.mm_iters
-        assert abs(res[b]["objective"] - ref.objective) <= obj_bar * ref.objective
-        assert err <= beta_bar
-        assert np.max(np.abs(beta[b] - singles[b].beta)) <= beta_bar * np.max(np.abs(singles[b].beta))
+        assert abs(res[b]["objective"] - ref.objective) <= obar * ref.objective
+        assert err <= ebar
+        # the single solve is another rounding of the same trajectory: within the bar of each, so twice
+        assert err_single <= 2 * ebar
 
 
 def test_grid_mixed_graphs_and_lambda1_zero(flr, ctx):

@@ -338,3 +338,31 @@ def test_profiling_leaves_solution_intact(flr, ctx):
     sb = b.solve(0.2, 0.4, tol=1e-6, use_last=1, max_iter=2)
     b.close()
     assert np.array_equal(sa.beta, sb.beta)
+
+
+@pytest.mark.parametrize("dtype", [flrgen.F32, flrgen.BF16])
+def test_mixed_refinement_reaches_fp64_residual(flr, ctx, dtype):
+    # iterative refinement: rounds of FP32-product PCG restart from the FP64 residual c - Q x until that
+    # true residual meets the inner tolerance (1e-10 here); the reported residual is that true FP64 one.
+    # The trajectory keeps the oracle's MM count and its objective (gap far below the 1e-6 the mixed path
+    # must hold).  beta is not held to the FP64 bar: a residual bound leaves the error free in the
+    # directions of Q's small eigenvalues, which the FP32 products excite and CG's own error does not
+    # (observed 2-4e-8 against 3e-9 for the oracle stopping its inner solves at 1e-10).
+    inst = flrgen.config2(n=200, p=2000, dtype=dtype)
+    prob = flr.Problem.from_instance(ctx, inst)
+    mixed = prob.solve(inst.lam1, inst.lam2, tol=1e-8, inner_tol=1e-10, precision=flr.FLR_PREC_MIXED_FP32)
+    plain = prob.solve(inst.lam1, inst.lam2, tol=1e-8, inner_tol=1e-10)
+    prob.close()
+    P = oracle.Problem.from_instance(inst)
+    ref = oracle.solve(P, inst.lam1, inst.lam2, tol=1e-8, inner_tol=INNER, method=oracle.ALG2)
+    scale = np.max(np.abs(ref.beta))
+    err = np.max(np.abs(mixed.beta - ref.beta)) / scale
+    gap = (oracle.objective(P, inst.lam1, inst.lam2, mixed.beta) - ref.objective) / ref.objective
+    print("  mixed mm=%d cg=%d rel_res=%.2e err=%.2e gap=%.1e | plain cg=%d" % (
+        mixed.mm_iters, mixed.cg_iters, mixed.rel_residual, err, gap, plain.cg_iters), flush=True)
+    assert mixed.status == flr.FLR_OK and mixed.mm_iters == ref.mm_iters
+    assert mixed.rel_residual <= 1e-10
+    assert abs(gap) <= 1e-9
+    assert err <= 1e-6
+    # restarts cost steps, but not many: within twice the FP64 path's count
+    assert mixed.cg_iters <= 2 * plain.cg_iters
