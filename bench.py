@@ -177,10 +177,10 @@ def main():
     dom_name, dom_us = ("gemv_a", a_us) if a_us >= b_us else ("gemv_b", b_us)
     achieved = alg_bytes / (dom_us * 1e-6) / 1e9
     traffic = measured_traffic(dom_name, wname)
-    # algorithmic bandwidth of the whole solve: two X passes per PCG step (X p, then X^T u) and two per
-    # MM boundary (X beta, X^T X beta), over the wall time of a solve
-    passes = 2 * s.cg_iters + 2 * s.mm_iters
-    solve_gbs = passes * inst.n * inst.p * xbytes / (elapsed / args.steps) / 1e9
+    # algorithmic bandwidth of the whole solve: per PCG step one pass over X (the one-pass bound of
+    # X^T X p) plus about twelve p-vectors, the same per MM boundary, over the wall time of a solve
+    step_bytes = inst.n * inst.p * xbytes + 12 * 8 * inst.p
+    solve_gbs = (s.cg_iters + s.mm_iters) * step_bytes / (elapsed / args.steps) / 1e9
 
     line = {
         "metric": METRIC,
