@@ -124,6 +124,19 @@ flr_status flr_create(flr_ctx ctx, const void* X, flr_dtype x_dtype, int64_t n, 
                       const double* y, const int64_t* edges, int64_t m, flr_problem* out);
 void flr_destroy(flr_problem h);
 
+/* Create a resident fused lasso signal approximation problem (X = I, n = p;
+ * the FLSA of the introduction, e.g. the 2-D image denoising of section 5.2):
+ * minimize 1/2 ||y - b||^2 + lambda1 sum |b_j| + lambda2 sum_E |b_j - b_k|.
+ * No X is stored or read: every solve runs the same MM / PCG iteration
+ * (Algorithm 2) with X^T X p = p, c = y and ||X_j||^2 = 1.  y: host, length p.
+ * edges as flr_create.  Every solve entry point accepts the handle (the grid
+ * uses U = V = O in place of the products); flr_profile_grid rejects it.
+ * Errors as flr_create. */
+flr_status flr_create_flsa(flr_ctx ctx, const double* y, int64_t p, const int64_t* edges, int64_t m,
+                           flr_problem* out);
+/* 1 for a handle made by flr_create_flsa, 0 otherwise, -1 for NULL. */
+int32_t flr_problem_is_flsa(flr_problem h);
+
 /* Solve at (lambda1, lambda2) to relative objective change tol (Algorithm 2).
  * beta_out_host: length p.  objective_out, iterations_out: nullable.
  * Errors: lambda < 0 or non-finite, tol <= 0 -> FLR_ERR_INVALID_ARG;

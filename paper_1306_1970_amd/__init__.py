@@ -30,7 +30,7 @@ EXPORTS = [
     "flr_solve_ex", "flr_solve_grid", "flr_problem_footprint", "flr_problem_n", "flr_problem_p", "flr_problem_m",
     "flr_server_create", "flr_server_submit", "flr_server_poll", "flr_server_stats", "flr_server_destroy",
     "flr_profile_kernels", "flr_profile_grid", "flr_status_string", "flr_last_error", "flr_solve_batch",
-    "flr_solve_grid_static", "flr_solve_path",
+    "flr_solve_grid_static", "flr_solve_path", "flr_create_flsa", "flr_problem_is_flsa",
 ]
 
 
@@ -71,6 +71,9 @@ def lib():
         L.flr_ctx_destroy.argtypes = [vp]
         L.flr_create.argtypes = [vp, vp, C.c_int, i64, i64, i64, vp, vp, i64, C.POINTER(vp)]
         L.flr_destroy.argtypes = [vp]
+        L.flr_create_flsa.argtypes = [vp, vp, i64, vp, i64, C.POINTER(vp)]
+        L.flr_problem_is_flsa.argtypes = [vp]
+        L.flr_problem_is_flsa.restype = i32
         L.flr_solve.argtypes = [vp, d, d, d, vp, C.POINTER(d), C.POINTER(i32)]
         L.flr_solve_ex.argtypes = [vp, d, d, d, C.POINTER(flr_solve_opts), vp, C.POINTER(flr_result)]
         L.flr_solve_grid.argtypes = [vp, vp, vp, i32, d, C.POINTER(flr_solve_opts), vp, vp]
@@ -158,6 +161,16 @@ def flr_create(ctx, X, x_dtype: int, n: int, p: int, ldx: int, y, edges, m: int)
 
 def flr_destroy(h):
     lib().flr_destroy(h)
+
+
+def flr_create_flsa(ctx, y, p: int, edges, m: int):
+    out = C.c_void_p()
+    _check(lib().flr_create_flsa(ctx, _ptr(y), p, _ptr(edges) if m else None, m, C.byref(out)))
+    return out
+
+
+def flr_problem_is_flsa(h) -> int:
+    return int(lib().flr_problem_is_flsa(h))
 
 
 def flr_solve(h, lambda1, lambda2, tol, beta_out):
@@ -342,6 +355,19 @@ class Problem:
     @classmethod
     def from_instance(cls, ctx, inst):
         return cls(ctx, inst.X, inst.dtype, inst.y, inst.edges)
+
+    @classmethod
+    def flsa(cls, ctx, y, edges):
+        """A fused lasso signal approximation problem (X = I): flr_create_flsa."""
+        self = cls.__new__(cls)
+        self.ctx = ctx
+        yv = np.ascontiguousarray(y, dtype=np.float64)
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.int64).reshape(-1, 2))
+        self.n = self.p = int(yv.size)
+        self.m_in = e.shape[0]
+        self._X = None
+        self.h = flr_create_flsa(ctx.h, yv, self.p, e, e.shape[0])
+        return self
 
     @property
     def footprint(self) -> int:

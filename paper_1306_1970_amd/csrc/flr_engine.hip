@@ -58,11 +58,12 @@ hipError_t dalloc(flr_problem h, T** p, size_t count) {
 
 int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
-Dims choose_dims(int64_t n, int64_t p, int dtype) {
+Dims choose_dims(int64_t n, int64_t p, int dtype, bool flsa) {
   Dims D{};
   D.n = n;
   D.p = p;
   D.dtype = dtype;
+  D.flsa = flsa ? 1 : 0;
   const int V = dtype == FLR_F64 ? 2 : dtype == FLR_F32 ? 4 : 8;
   D.c1 = 256 * V;
   D.c2 = 64 * V;
@@ -87,8 +88,15 @@ Dims choose_dims(int64_t n, int64_t p, int dtype) {
   if (r2 > kMaxR2) r2 = kMaxR2;
   D.r2 = (int32_t)r2;
   D.rb2 = (int32_t)((n + r2 - 1) / r2);
+  if (flsa) {  // X = I: one row panel per column panel, nothing streamed
+    D.rb1 = 1;
+    D.r1 = (int32_t)std::min<int64_t>(n, INT32_MAX);
+    D.rb2 = 1;
+    D.r2 = 0;
+  }
   D.nblk = (int32_t)(D.p_pad / kBlk);
   D.gridB = std::max(D.cb2 * D.rb2, D.nblk);
+  D.nloss = flsa ? D.cb2 : D.rb2;
   return D;
 }
 
@@ -367,9 +375,11 @@ static void problem_free(flr_problem h) {
   delete h;
 }
 
-flr_status flr_create(flr_ctx ctx, const void* X, flr_dtype x_dtype, int64_t n, int64_t p, int64_t ldx,
-                      const double* y, const int64_t* edges, int64_t m, flr_problem* out) {
-  if (!ctx || !X || !y || !out) return fail(FLR_ERR_INVALID_ARG, "NULL argument");
+// X == nullptr: the fused lasso signal approximation (X = I, n = p).
+static flr_status create_impl(flr_ctx ctx, const void* X, flr_dtype x_dtype, int64_t n, int64_t p, int64_t ldx,
+                              const double* y, const int64_t* edges, int64_t m, flr_problem* out) {
+  const bool flsa = X == nullptr;
+  if (!ctx || !y || !out) return fail(FLR_ERR_INVALID_ARG, "NULL argument");
   if (n < 1 || p < 1 || ldx < p) return fail(FLR_ERR_INVALID_ARG, "need n >= 1, p >= 1, ldx >= p");
   if (x_dtype != FLR_F64 && x_dtype != FLR_F32 && x_dtype != FLR_BF16)
     return fail(FLR_ERR_INVALID_ARG, "unknown x_dtype");
@@ -416,7 +426,7 @@ flr_status flr_create(flr_ctx ctx, const void* X, flr_dtype x_dtype, int64_t n, 
   h->ctx = ctx;
   h->m = mm;
   h->nnz = 2 * mm;
-  h->D = choose_dims(n, p, x_dtype);
+  h->D = choose_dims(n, p, x_dtype, flsa);
   const Dims& D = h->D;
   auto bail = [&](flr_status st) {
     problem_free(h);
@@ -436,7 +446,7 @@ flr_status flr_create(flr_ctx ctx, const void* X, flr_dtype x_dtype, int64_t n, 
   CK(hipHostMalloc(reinterpret_cast<void**>(&h->h_state), 2 * sizeof(State), hipHostMallocDefault));
   const size_t xb = x_dtype == FLR_F64 ? 8 : x_dtype == FLR_F32 ? 4 : 2;
   void* Xd = nullptr;
-  {
+  if (!flsa) {
     size_t bytes = (size_t)n * (size_t)D.ldx * xb;
     CK(hipMalloc(&Xd, bytes));
     h->allocs.push_back(Xd);
@@ -471,7 +481,7 @@ flr_status flr_create(flr_ctx ctx, const void* X, flr_dtype x_dtype, int64_t n, 
   CK(dalloc(h, &B.upart, (size_t)D.cb1 * (size_t)n));
   CK(dalloc(h, &B.qpart, (size_t)D.rb2 * (size_t)D.p_pad));
   CK(dalloc(h, &B.pqpart, (size_t)D.gridB));
-  CK(dalloc(h, &B.losspart, (size_t)D.rb2));
+  CK(dalloc(h, &B.losspart, (size_t)std::max(D.rb2, D.cb2)));
   CK(dalloc(h, &B.penpart, (size_t)D.nblk));
   CK(dalloc(h, &B.blk, (size_t)BK_N * (size_t)D.nblk));
   CK(dalloc(h, &B.carry, 2 * (size_t)D.nblk));
@@ -503,19 +513,28 @@ flr_status flr_create(flr_ctx ctx, const void* X, flr_dtype x_dtype, int64_t n, 
   CK(hipMemcpyAsync(rp, rowptr.data(), rowptr.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
   CK(hipMemcpyAsync(cl, col.data(), col.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
   CK(hipMemcpyAsync(pp, prevpos.data(), prevpos.size() * sizeof(int32_t), hipMemcpyHostToDevice, h->stream));
-  CK(launch_check_finite(Xd, x_dtype, (int64_t)n * D.ldx, flag, h->stream));
-  // setup partials reuse the q/u work areas: qpart holds rb2 x p_pad doubles
-  cpart = B.qpart;
-  double* tmp2 = nullptr;
-  CK(hipMalloc(reinterpret_cast<void**>(&tmp2), (size_t)D.rb2 * (size_t)D.p_pad * sizeof(double)));
-  spart = tmp2;
-  CK(launch_setup(D, Xd, yd, cpart, spart, c, s, h->stream));
   int hflag = 0;
-  CK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   std::vector<double> hc((size_t)D.p);
-  CK(hipMemcpyAsync(hc.data(), c, (size_t)D.p * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-  CK(hipStreamSynchronize(h->stream));
-  (void)hipFree(tmp2);
+  if (!flsa) {
+    CK(launch_check_finite(Xd, x_dtype, (int64_t)n * D.ldx, flag, h->stream));
+    // setup partials reuse the q/u work areas: qpart holds rb2 x p_pad doubles
+    cpart = B.qpart;
+    double* tmp2 = nullptr;
+    CK(hipMalloc(reinterpret_cast<void**>(&tmp2), (size_t)D.rb2 * (size_t)D.p_pad * sizeof(double)));
+    spart = tmp2;
+    CK(launch_setup(D, Xd, yd, cpart, spart, c, s, h->stream));
+    CK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    CK(hipMemcpyAsync(hc.data(), c, (size_t)D.p * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    CK(hipStreamSynchronize(h->stream));
+    (void)hipFree(tmp2);
+  } else {
+    // X = I: c = X^T y = y, ||X_j||^2 = 1 (the padding keeps zeros from dalloc)
+    std::vector<double> ones((size_t)D.p, 1.0);
+    CK(hipMemcpyAsync(c, y, (size_t)D.p * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    CK(hipMemcpyAsync(s, ones.data(), (size_t)D.p * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    CK(hipStreamSynchronize(h->stream));
+    std::copy(y, y + D.p, hc.begin());
+  }
   if (hflag) return bail(fail(FLR_ERR_INVALID_ARG, "X has a non-finite value"));
   double cn = 0.0;
   for (double v : hc) cn += v * v;
@@ -524,6 +543,19 @@ flr_status flr_create(flr_ctx ctx, const void* X, flr_dtype x_dtype, int64_t n, 
   *out = h;
   return FLR_OK;
 }
+
+flr_status flr_create(flr_ctx ctx, const void* X, flr_dtype x_dtype, int64_t n, int64_t p, int64_t ldx,
+                      const double* y, const int64_t* edges, int64_t m, flr_problem* out) {
+  if (!X) return fail(FLR_ERR_INVALID_ARG, "NULL argument");
+  return create_impl(ctx, X, x_dtype, n, p, ldx, y, edges, m, out);
+}
+
+flr_status flr_create_flsa(flr_ctx ctx, const double* y, int64_t p, const int64_t* edges, int64_t m,
+                           flr_problem* out) {
+  return create_impl(ctx, nullptr, FLR_F64, p, p, p, y, edges, m, out);
+}
+
+int32_t flr_problem_is_flsa(flr_problem h) { return h ? h->D.flsa : -1; }
 
 void flr_destroy(flr_problem h) { problem_free(h); }
 

@@ -557,6 +557,13 @@ __global__ __launch_bounds__(kWG) void k_fill_zero(double* __restrict__ p, int64
 // U = X O, then V = X^T U, for the first nact operand columns.
 static hipError_t grid_products(flr_problem h, const GridWork& gw, const GridDev& G, const double* O, int nact) {
   const Dims& D = h->D;
+  if (D.flsa) {  // X = I: U = O (its p rows) and V = X^T U = O
+    hipError_t e = hipMemcpy2DAsync(G.U, (size_t)G.ldu * sizeof(double), O, (size_t)D.p_pad * sizeof(double),
+                                    (size_t)D.p * sizeof(double), (size_t)nact, hipMemcpyDeviceToDevice, h->stream);
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(G.V, O, (size_t)nact * (size_t)D.p_pad * sizeof(double), hipMemcpyDeviceToDevice,
+                          h->stream);
+  }
   GemmArgs a{};
   a.X = h->B.X;
   a.ldx = D.ldx;
@@ -849,6 +856,7 @@ extern "C" flr_status flr_profile_grid(flr_problem h, int32_t B, int32_t reps, d
   if (!lk.owns_lock()) return gfail(FLR_ERR_BUSY, "problem handle in use by another thread");
   if (!h->grid || h->grid->cap < B)
     return gfail(FLR_ERR_INVALID_ARG, "flr_profile_grid: needs a completed grid solve with at least B columns");
+  if (h->D.flsa) return gfail(FLR_ERR_INVALID_ARG, "flr_profile_grid: an X = I problem has no products to time");
   if (hipSetDevice(h->ctx->device) != hipSuccess) return gfail(FLR_ERR_DEVICE, "hipSetDevice failed");
   GridWork* gw = h->grid;
   const GridDev& G = gw->G;

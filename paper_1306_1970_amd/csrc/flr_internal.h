@@ -75,6 +75,8 @@ struct Dims {
   int32_t c2, cb2, r2, rb2;
   int32_t nblk;
   int32_t gridB;          // max(cb2*rb2, nblk)
+  int32_t flsa;           // 1: X = I (fused lasso signal approximation), no X is stored or read
+  int32_t nloss;          // loss partials the block kernel sums (rb2, or cb2 when X = I)
 };
 
 struct Bufs {

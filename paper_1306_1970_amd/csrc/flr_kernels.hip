@@ -204,7 +204,7 @@ __global__ __launch_bounds__(kWG) void k_gemv_a(Dims D, Bufs B, const State* __r
     }
   }
   RAW cur0[NV], cur1[NV];
-  {
+  if (!D.flsa) {
     const int64_t i0 = r0 + wave, i1 = i0 + 4;
 #pragma unroll
     for (int t = 0; t < NV; ++t) {
@@ -228,6 +228,7 @@ __global__ __launch_bounds__(kWG) void k_gemv_a(Dims D, Bufs B, const State* __r
     for (int u = 0; u < V; ++u) sh_v[tid + u * kWG] = fy[u];
   }
   __syncthreads();
+  if (D.flsa) return;  // X = I: the column-panel kernel uses the operand itself
 
   if (MX && s.phase == PH_CG)
     rows_a<XT, float>(D, B, Xb, cb, r0, r1, c0, lane, wave, sh_v, cur0, cur1);
@@ -315,16 +316,43 @@ __global__ __launch_bounds__(kWG) void k_gemv_b(Dims D, Bufs B, const State* __r
   constexpr int CBMAX = 12;
   const int nr = (int)(r1 - r0);
   double upre[CBMAX];
-#pragma unroll
-  for (int q = 0; q < CBMAX; ++q) upre[q] = (tid < nr && q < D.cb1) ? B.upart[(int64_t)q * D.n + r0 + tid] : 0.0;
   RAW cur[RU];
+  if (!D.flsa) {
 #pragma unroll
-  for (int u = 0; u < RU; ++u) {
-    const int64_t i = r0 + wave + 4 * u;
-    if (i < r1) cur[u] = load16(Xb + i * D.ldx + c0);
+    for (int q = 0; q < CBMAX; ++q) upre[q] = (tid < nr && q < D.cb1) ? B.upart[(int64_t)q * D.n + r0 + tid] : 0.0;
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const int64_t i = r0 + wave + 4 * u;
+      if (i < r1) cur[u] = load16(Xb + i * D.ldx + c0);
+    }
   }
 
-  if (wg < ngemm) {
+  if (D.flsa && wg < ngemm) {
+    // X = I (one row panel): X^T X v = v; at an MM boundary the loss partial
+    // 1/2 ||y - x||^2 runs over this panel's coordinates
+    double dotp = 0.0, loss = 0.0;
+    for (int t = tid; t < 64 * V; t += kWG) {
+      const int64_t j = (int64_t)cb * D.c2 + t;
+      double q = 0.0;
+      if (j < D.p) {
+        q = pv[j];
+        if (cg) q += apply_m(B, prm, j, pv);
+        if (!cg) {
+          const double dlt = B.y[j] - pv[j];
+          loss = fma(dlt, dlt, loss);
+        }
+      }
+      B.qpart[j] = q;
+      if (cg) dotp = fma(pv[j], q, dotp);
+    }
+    if (cg) {
+      const double tot = wg_sum(dotp, sh_s);
+      if (tid == 0) B.pqpart[wg] = tot;
+    } else {
+      const double tot = wg_sum(loss, sh_s);
+      if (tid == 0) B.losspart[cb] = tot;
+    }
+  } else if (wg < ngemm) {
     double loss = 0.0;
     for (int t = tid; t < nr; t += kWG) {
       double u = 0.0;
@@ -807,7 +835,7 @@ __global__ __launch_bounds__(kWG) void k_block(Dims D, Bufs B, const State* __re
   }
   // f(b) = loss + penalties (identical arithmetic in every workgroup)
   double fpart = 0.0;
-  for (int q = tid; q < D.rb2; q += kWG) fpart += B.losspart[q];
+  for (int q = tid; q < D.nloss; q += kWG) fpart += B.losspart[q];
   const double loss = wg_sum(fpart, lds);
   double ppart = 0.0;
   for (int q = tid; q < D.nblk; q += kWG) ppart += B.penpart[q];
