@@ -38,6 +38,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FLR solves/sec at p=10k + HBM GB/s; batched/mixed vs plain at 1e-6 obj gap"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6  # dense FP64 MFMA
 
 
 def kernel_source_hash() -> str:
@@ -106,6 +107,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--method", default="pcg", choices=["pcg", "cholesky"],
+                    help="c1: Algorithm 2 (PCG) or Algorithm 1 (dense Cholesky per MM iteration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-mm-sample", type=int, default=60,
                     help="oracle baseline: MM iterations sampled (about 20 s on 16 host threads for c2)")
@@ -126,6 +129,8 @@ def main():
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-ps", default="1000,5000,10000,50000")
     ap.add_argument("--serve-tol", type=float, default=1e-6)
+    ap.add_argument("--serve-allpairs", default="pcg", choices=["pcg", "cholesky"],
+                    help="c5: method for the all-pairs requests (PCG or Algorithm 1's dense Cholesky)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: runs on one GPU only; --gpus %d is not supported (each GPU would take its own "
@@ -142,6 +147,8 @@ def main():
         return serve_main(args, flr)
     if args.workload == "c3":
         return grid_main(args, flr)
+    if args.method == "cholesky":
+        return dense_main(args, flr)
     inst, wname = make_workload(args.workload)
     print("bench: workload %s n=%d p=%d m=%d dtype=%s" % (wname, inst.n, inst.p, inst.m, inst.dtype),
           file=sys.stderr, flush=True)
@@ -224,6 +231,83 @@ def main():
     print(json.dumps(line), flush=True)
 
 
+def dense_main(args, flr):
+    """Algorithm 1 on the GPU: per MM iteration the dense system is assembled,
+    factored by the blocked FP64 Cholesky on the matrix cores and solved."""
+    import torch
+
+    if args.workload != "c1":
+        sys.exit("bench.py: --method cholesky runs on c1 (Algorithm 1 keeps dense p x p matrices; p <= 8192)")
+    import oracle
+
+    inst, wname = make_workload(args.workload)
+    print("bench: workload %s n=%d p=%d m=%d (Algorithm 1)" % (wname, inst.n, inst.p, inst.m), file=sys.stderr,
+          flush=True)
+    ctx = flr.Context(0)
+    prob = flr.Problem.from_instance(ctx, inst)
+    out = torch.zeros(inst.p, dtype=torch.float64, device="cuda:0")
+
+    def one():
+        return prob.solve(inst.lam1, inst.lam2, tol=inst.tol, out=out, method=flr.FLR_METHOD_CHOLESKY,
+                          max_iter=args.mm_cap)
+
+    for _ in range(args.warmup):
+        s = one()
+        print("bench: warmup solve mm=%d f=%.12g %.3fs" % (s.mm_iters, s.objective, s.seconds), file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sols = []
+    for _ in range(args.steps):
+        sols.append(one())
+        print("bench: solve mm=%d f=%.12g %.3fs" % (sols[-1].mm_iters, sols[-1].objective, sols[-1].seconds),
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    s = sols[-1]
+    want = flr.FLR_ERR_MAX_ITER if args.mm_cap else flr.FLR_OK
+    assert all(x.status in (flr.FLR_OK, want) for x in sols), [x.status for x in sols]
+    asm_us, fac_us, sol_us = flr.flr_profile_dense(prob.h, inst.lam1, inst.lam2, args.profile_reps)
+    fac_flops = inst.p ** 3 / 3.0  # Cholesky of the p x p system (the padding to 64 is not counted)
+    achieved = fac_flops / (fac_us * 1e-6) / 1e12
+    line = {
+        "metric": METRIC,
+        "value": args.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wname, "method": "algorithm1_cholesky", "n": inst.n, "p": inst.p,
+                   "graph": inst.graph, "x_storage": {0: "f64", 1: "f32", 2: "bf16"}[inst.dtype],
+                   "lambda1": inst.lam1, "lambda2": inst.lam2, "tol": inst.tol, "eps": inst.eps,
+                   "mm_iters": s.mm_iters, "objective": s.objective,
+                   "ms_per_mm_iteration": 1000.0 * elapsed / args.steps / max(s.mm_iters, 1)},
+        "roofline": {"bound": "mfma", "kernel": "cholesky_factor", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None, "avg_us": fac_us,
+                     "avg_us_how": "HIP events around each of %d factorizations (%d launches each) on the "
+                                   "problem's stream" % (args.profile_reps, 3 * ((inst.p + 63) // 64)),
+                     "algorithmic_flops": fac_flops, "assembly_us": asm_us, "triangular_solves_us": sol_us},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        P = oracle.Problem.from_instance(inst)
+        t0 = time.perf_counter()
+        r = oracle.solve(P, inst.lam1, inst.lam2, eps=inst.eps, tol=inst.tol, method=oracle.ALG1)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": 1.0 / dt, "unit": "solves/s", "cores": int(r.threads), "kind": "oracle",
+                                "sample": "one complete Algorithm 1 solve (%d MM iterations) in %.1f s on %d threads"
+                                          % (r.mm_iters, dt, r.threads)}
+    prob.close()
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def grid_main(args, flr):
     """Batched lambda grid against the plain path on the same GPU."""
     import numpy as np
@@ -288,7 +372,7 @@ def grid_main(args, flr):
                    "status": int(st), "mm_iters_max": max(r["mm_iters"] for r in res),
                    "cg_iters_max": max(r["cg_iters"] for r in res)},
         "roofline": {"bound": "mfma", "kernel": "gemm_XO" if ua >= va else "gemm_XtU", "achieved": achieved,
-                     "peak": 78.6, "unit": "TFLOP/s", "frac": achieved / 78.6, "traffic": None,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
                      "avg_us": dom_us, "algorithmic_flops": flops, "other_kernel_us": min(ua, va)},
     }
     print(json.dumps(line), flush=True)
@@ -321,6 +405,8 @@ def serve_main(args, flr):
     budget = int(args.serve_budget_gib * 2 ** 30)
     srv = flr.flr_server_create(ctx.h, budget, args.serve_slots)
     opts = flr.default_opts(use_last=1)
+    m_ap = flr.FLR_METHOD_CHOLESKY if args.serve_allpairs == "cholesky" else flr.FLR_METHOD_PCG
+    opts_ap = flr.default_opts(use_last=1, method=m_ap)
     tickets = [None] * len(reqs)
     t0 = time.perf_counter()
 
@@ -330,15 +416,17 @@ def serve_main(args, flr):
             if wait > 0:
                 time.sleep(wait)
             h = cells[(r["p"], r["graph"], r["slot"] % args.serve_instances)].h
-            tickets[i] = flr.flr_server_submit(srv, h, r["lam1"], r["lam2"], args.serve_tol, opts)
+            o = opts_ap if r["graph"] == "allpairs" else opts
+            tickets[i] = flr.flr_server_submit(srv, h, r["lam1"], r["lam2"], args.serve_tol, o)
 
     th = threading.Thread(target=submitter)
     th.start()
     th.join()
-    lat, mm, cg, status = [], 0, 0, {}
+    lat, mm, cg, status, by_graph = [], 0, 0, {}, {}
     for i, t in enumerate(tickets):
         st, res = flr.flr_server_poll(srv, t, True)
         lat.append(res.seconds)
+        by_graph.setdefault(reqs[i]["graph"], []).append(res.seconds)
         mm += res.mm_iters
         cg += res.cg_iters
         status[st] = status.get(st, 0) + 1
@@ -369,6 +457,8 @@ def serve_main(args, flr):
                    "resident_problems": len(cells), "budget_bytes": budget, "tol": args.serve_tol,
                    "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
                    "max_s": float(lat.max()), "mm_iters": mm, "cg_iters": cg,
+                   "allpairs_method": args.serve_allpairs,
+                   "p50_s_by_graph": {g: float(np.percentile(v, 50)) for g, v in sorted(by_graph.items())},
                    "status_counts": {str(k): v for k, v in status.items()}},
     }
     print(json.dumps(line), flush=True)

@@ -82,6 +82,18 @@ typedef enum {
   FLR_PRECOND_BAND = 3
 } flr_precond;
 
+/* How each MM iteration solves its linear system (section 3.1).
+ *   PCG       Algorithm 2: preconditioned conjugate gradients with M = lambda1 A
+ *             + lambda2 B (the default; every entry point).
+ *   CHOLESKY  Algorithm 1: the whole system Q = X^T X + lambda1 A + lambda2 B is
+ *             formed (X^T X once per handle) and solved through its Cholesky
+ *             factor; exact inner solves, cg_iters = 0.  The paper's route for a
+ *             general edge set.  Needs p <= 8192 (two dense p x p FP64 matrices,
+ *             allocated on first use and charged to the footprint); flr_solve,
+ *             flr_solve_ex, flr_solve_path and the server only (the grid and
+ *             the ragged batch reject it). */
+typedef enum { FLR_METHOD_PCG = 0, FLR_METHOD_CHOLESKY = 1 } flr_method;
+
 typedef struct {
   double eps;              /* perturbation; 0 -> 1e-8 (section 5) */
   double inner_tol;        /* PCG stop ||r|| / ||X^T y||; 0 -> tol (Algorithm 2 uses one delta) */
@@ -92,7 +104,7 @@ typedef struct {
   const double* warm_start;/* host or device, length p; NULL -> the handle's last beta if
                               use_last is set and a solve has run, else X_j^T y / X_j^T X_j */
   int32_t use_last;        /* 1: warm-start from the handle's previous solution */
-  int32_t reserved;
+  int32_t method;          /* flr_method: how each MM iteration solves its linear system */
 } flr_solve_opts;
 
 typedef struct {
@@ -253,6 +265,16 @@ flr_status flr_profile_kernels(flr_problem h, int32_t reps, double* avg_us);
  * grid workspace's scratch operand, so it needs a completed grid solve with at
  * least B columns on the handle; solver state is not touched. */
 flr_status flr_profile_grid(flr_problem h, int32_t B, int32_t reps, double* avg_us);
+
+/* Profiling of Algorithm 1 (section 3.1): at the handle's current iterate,
+ * run `reps` times each (a) the reweighting and assembly of Q = X^T X +
+ * lambda1 A + lambda2 B, (b) the blocked Cholesky factor Q = L L^T and (c) the
+ * forward and backward triangular solves, on the problem's stream, and report
+ * their average durations in microseconds (HIP events; avg_us: host, 3
+ * entries).  Needs a completed FLR_METHOD_CHOLESKY solve on the handle (its
+ * dense workspace); the iterate and the last result are left intact.
+ * FLR_ERR_INVALID_ARG without that workspace or with negative lambdas. */
+flr_status flr_profile_dense(flr_problem h, double lambda1, double lambda2, int32_t reps, double* avg_us);
 
 const char* flr_status_string(flr_status st);
 const char* flr_last_error(void);

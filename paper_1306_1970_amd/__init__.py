@@ -23,13 +23,14 @@ FLR_ERR_NUMERICAL, FLR_ERR_MAX_ITER, FLR_ERR_BUSY, FLR_ERR_NOT_READY = 4, 5, 6, 
 FLR_F64, FLR_F32, FLR_BF16 = 0, 1, 2
 FLR_PREC_FP64, FLR_PREC_MIXED_FP32 = 0, 1
 FLR_PRECOND_AUTO, FLR_PRECOND_TRIDIAG, FLR_PRECOND_JACOBI, FLR_PRECOND_BAND = 0, 1, 2, 3
+FLR_METHOD_PCG, FLR_METHOD_CHOLESKY = 0, 1
 
 # every symbol include/flr.h declares
 EXPORTS = [
     "flr_default_opts", "flr_ctx_create", "flr_ctx_destroy", "flr_create", "flr_destroy", "flr_solve",
     "flr_solve_ex", "flr_solve_grid", "flr_problem_footprint", "flr_problem_n", "flr_problem_p", "flr_problem_m",
     "flr_server_create", "flr_server_submit", "flr_server_poll", "flr_server_stats", "flr_server_destroy",
-    "flr_profile_kernels", "flr_profile_grid", "flr_status_string", "flr_last_error", "flr_solve_batch",
+    "flr_profile_kernels", "flr_profile_grid", "flr_profile_dense", "flr_status_string", "flr_last_error", "flr_solve_batch",
     "flr_solve_grid_static", "flr_solve_path", "flr_create_flsa", "flr_problem_is_flsa",
 ]
 
@@ -43,7 +44,7 @@ class FlrError(RuntimeError):
 class flr_solve_opts(C.Structure):
     _fields_ = [("eps", C.c_double), ("inner_tol", C.c_double), ("max_iter", C.c_int32), ("max_cg", C.c_int32),
                 ("precision", C.c_int32), ("preconditioner", C.c_int32), ("warm_start", C.c_void_p),
-                ("use_last", C.c_int32), ("reserved", C.c_int32)]
+                ("use_last", C.c_int32), ("method", C.c_int32)]
 
 
 class flr_result(C.Structure):
@@ -90,6 +91,7 @@ def lib():
         L.flr_server_destroy.argtypes = [vp]
         L.flr_profile_kernels.argtypes = [vp, i32, vp]
         L.flr_profile_grid.argtypes = [vp, i32, i32, vp]
+        L.flr_profile_dense.argtypes = [vp, d, d, i32, vp]
         L.flr_solve_batch.argtypes = [vp, i32, vp, vp, d, C.POINTER(flr_solve_opts), vp, vp]
         L.flr_status_string.argtypes = [C.c_int]
         L.flr_status_string.restype = C.c_char_p
@@ -284,6 +286,13 @@ def flr_solve_batch(problems, lambda1, lambda2, tol, opts=None, betas=None):
                                C.cast(outs, C.c_void_p) if outs is not None else None, C.cast(res, C.c_void_p))
     _check(st, ok=(FLR_OK, FLR_ERR_MAX_ITER, FLR_ERR_NUMERICAL))
     return st, list(res)
+
+
+def flr_profile_dense(h, lam1: float, lam2: float, reps: int):
+    """Average durations (us) of one Algorithm 1 step's assembly, Cholesky factor and triangular solves."""
+    out = np.zeros(3)
+    _check(lib().flr_profile_dense(h, lam1, lam2, reps, out.ctypes.data))
+    return float(out[0]), float(out[1]), float(out[2])
 
 
 def flr_profile_grid(h, B: int, reps: int):

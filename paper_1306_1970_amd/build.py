@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libflr.so")
-SOURCES = ["flr_kernels.hip", "flr_engine.hip", "flr_grid.hip", "flr_gemm.hip", "flr_server.hip"]
+SOURCES = ["flr_kernels.hip", "flr_engine.hip", "flr_grid.hip", "flr_gemm.hip", "flr_dense.hip", "flr_server.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=" + ARCH, "-fPIC", "-Wall", "-Wno-unused-function",

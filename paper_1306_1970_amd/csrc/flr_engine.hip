@@ -265,6 +265,11 @@ flr_status solve_end(SolveRun& run, double* beta_out, flr_result* res) {
 // One solve on the problem's stream; beta_out host or device (or nullptr).
 flr_status run_solve(flr_problem h, double l1, double l2, double tol, const flr_solve_opts* o, double* beta_out,
                      flr_result* res) {
+  if (o && o->method != FLR_METHOD_PCG) {
+    if (o->method != FLR_METHOD_CHOLESKY) return fail(FLR_ERR_INVALID_ARG, "unknown method");
+    if (!(o->eps >= 0.0) || o->max_iter < 0) return fail(FLR_ERR_INVALID_ARG, "options out of range");
+    return dense_run(h, l1, l2, tol, o, beta_out, res);
+  }
   SolveRun run;
   flr_status st = solve_begin(h, l1, l2, tol, o, run);
   if (st != FLR_OK) return st;
@@ -361,6 +366,7 @@ static void problem_free(flr_problem h) {
   if (!h) return;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   flr::grid_free(h);
+  flr::dense_free(h);
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b) {
       if (h->gexec[a][b]) (void)hipGraphExecDestroy(h->gexec[a][b]);
@@ -609,6 +615,8 @@ flr_status flr_solve_batch(const flr_problem* hs, int32_t count, const double* l
     if (!locks.back().owns_lock()) return fail(FLR_ERR_BUSY, "flr_solve_batch: a problem handle is in use");
   }
   if (hipSetDevice(hs[0]->ctx->device) != hipSuccess) return fail(FLR_ERR_DEVICE, "hipSetDevice failed");
+  if (opts && opts->method != FLR_METHOD_PCG)
+    return fail(FLR_ERR_INVALID_ARG, "flr_solve_batch runs Algorithm 2 (PCG) only");
   std::vector<SolveRun> runs((size_t)count);
   for (int32_t i = 0; i < count; ++i) {
     flr_status st = solve_begin(hs[i], l1[i], l2[i], tol, opts, runs[(size_t)i]);
@@ -684,6 +692,15 @@ flr_status flr_solve_path(flr_problem h, const double* l1, const double* l2, con
     if (st != FLR_OK && first == FLR_OK) first = st;
   }
   return first;
+}
+
+flr_status flr_profile_dense(flr_problem h, double lambda1, double lambda2, int32_t reps, double* avg_us) {
+  if (!h || reps < 1 || !avg_us || !(lambda1 >= 0.0) || !(lambda2 >= 0.0))
+    return fail(FLR_ERR_INVALID_ARG, "bad profiling arguments");
+  std::unique_lock<std::mutex> lk(h->busy, std::try_to_lock);
+  if (!lk.owns_lock()) return fail(FLR_ERR_BUSY, "problem handle in use by another thread");
+  HIP_OR_FAIL(hipSetDevice(h->ctx->device));
+  return dense_profile(h, lambda1, lambda2, reps, avg_us);
 }
 
 flr_status flr_profile_kernels(flr_problem h, int32_t reps, double* avg_us) {

@@ -40,5 +40,6 @@ constexpr int kGemmKT = 32;  // reduction depth staged per LDS tile
 
 hipError_t launch_gemm_xo(int dtype, const GemmArgs& g, hipStream_t st);   // U = X O (split over K)
 hipError_t launch_gemm_xtu(int dtype, const GemmArgs& g, hipStream_t st);  // V = X^T U
+hipError_t launch_gram(int dtype, const GemmArgs& g, hipStream_t st);      // C = X^T X (M = N = columns)
 
 }  // namespace flr

@@ -45,7 +45,8 @@ __device__ inline void load8d(const double* p, double (&v)[8]) {
 // TR = false: C (M = n) = X O, reduction over the columns of X, split over K
 //             into nslice partial outputs.
 // TR = true:  C (M = p_pad) = X^T U, reduction over the n rows of X.
-template <typename XT, bool TR>
+// BX (with TR): the right operand is X as well, C = X^T X (the Gram matrix).
+template <typename XT, bool TR, bool BX = false>
 __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
   constexpr int MT = kGemmMT, NT = kGemmNT, KT = kGemmKT, LDK = KT + 2;
   __shared__ __align__(16) double As[2][MT * LDK];  // [m][k]
@@ -84,6 +85,16 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
         for (int e = 0; e < 8; ++e) ra[e] = 0.0;
       }
     }
+    if (BX) {  // B(n, k) = X[k][n]: row k0 + kr of X, columns n0 + c ..
+      const int kr = tid >> 3, c = (tid & 7) * 8;
+      if (k0 + kr < g.K) {
+        load8x(X + (k0 + kr) * g.ldx + n0 + c, rb);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) rb[e] = 0.0;
+      }
+      return;
+    }
     const int cn = tid >> 2, cc = (tid & 3) * 8;  // operand column n0 + cn, entries k0 + cc ..
     if (n0 + cn < g.N) {
       load8d(g.Bm + (int64_t)(n0 + cn) * g.ldb + k0 + cc, rb);
@@ -101,6 +112,12 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
       const int kr = tid >> 3, c = (tid & 7) * 8;
 #pragma unroll
       for (int e = 0; e < 8; ++e) As[buf][(c + e) * LDK + kr] = ra[e];
+    }
+    if (BX) {
+      const int kr = tid >> 3, c = (tid & 7) * 8;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) Bs[buf][(c + e) * LDK + kr] = rb[e];
+      return;
     }
     const int cn = tid >> 2, cc = (tid & 3) * 8;
 #pragma unroll
@@ -158,12 +175,20 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
     }
 }
 
-template <typename XT, bool TR>
+template <typename XT, bool TR, bool BX = false>
 static hipError_t launch_t(const GemmArgs& g, hipStream_t st) {
   const int T = g.tiles_m * g.tiles_n * g.nslice;
   const int grid = 8 * ((T + 7) / 8);
-  hipLaunchKernelGGL((k_gemm_f64<XT, TR>), dim3(grid), dim3(256), 0, st, g);
+  hipLaunchKernelGGL((k_gemm_f64<XT, TR, BX>), dim3(grid), dim3(256), 0, st, g);
   return hipGetLastError();
+}
+
+hipError_t launch_gram(int dtype, const GemmArgs& g, hipStream_t st) {
+  switch (dtype) {
+    case 0: return launch_t<double, true, true>(g, st);
+    case 1: return launch_t<float, true, true>(g, st);
+    default: return launch_t<uint16_t, true, true>(g, st);
+  }
 }
 
 hipError_t launch_gemm_xo(int dtype, const GemmArgs& g, hipStream_t st) {

@@ -819,6 +819,7 @@ static flr_status grid_check(flr_problem h, const double* l1, const double* l2, 
   }
   if (!(std::isfinite(tol) && tol > 0.0)) return gfail(FLR_ERR_INVALID_ARG, "tol must be finite and > 0");
   if (o->precision != FLR_PREC_FP64) return gfail(FLR_ERR_INVALID_ARG, "grid solves run in FP64 (no mixed-precision grid path)");
+  if (o->method != FLR_METHOD_PCG) return gfail(FLR_ERR_INVALID_ARG, "the grid runs Algorithm 2 (PCG) only");
   if (!(o->eps >= 0.0) || !(o->inner_tol >= 0.0) || o->max_iter < 0 || o->max_cg < 0)
     return gfail(FLR_ERR_INVALID_ARG, "options out of range");
   const int pre0 = o->preconditioner;

@@ -11,6 +11,9 @@
 #include "flr_internal.h"
 
 struct GridWork;  // batched-grid workspace (flr_grid.hip)
+namespace flr {
+struct DenseWork;  // Algorithm 1 workspace (flr_dense.hip)
+}
 using flr::Bufs;
 using flr::Dims;
 using flr::Params;
@@ -47,10 +50,15 @@ struct flr_problem_s {
   std::mutex busy;
   int64_t edges_m = 0;
   GridWork* grid = nullptr;  // workspace of the last grid solve (kept while large enough)
+  flr::DenseWork* dense = nullptr;  // Algorithm 1: X^T X and the dense system (first use)
 };
 
 
 namespace flr {
 void set_last_error(const std::string& s);
 void grid_free(flr_problem h);
+void dense_free(flr_problem h);
+flr_status dense_run(flr_problem h, double l1, double l2, double tol, const flr_solve_opts* o, double* beta_out,
+                     flr_result* res);
+flr_status dense_profile(flr_problem h, double l1, double l2, int32_t reps, double* avg_us);
 }  // namespace flr

@@ -27,6 +27,7 @@ import pytest
 
 import flrgen
 import oracle
+from spread import oracle_with_spread as _oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -49,29 +50,6 @@ def ctx(flr):
     c = flr.Context(0)
     yield c
     c.close()
-
-
-def _reversed(inst):
-    p = inst.p
-    return oracle.Problem(np.ascontiguousarray(inst.X[:, ::-1]), inst.dtype, inst.y,
-                          np.ascontiguousarray((p - 1 - inst.edges)[:, ::-1]))
-
-
-def _oracle(inst, lam1, lam2, ulp_samples=2, **kw):
-    """Oracle result and its rounding spread on this case: the largest change of beta when the oracle runs
-    with every product summed in reverse order, or with y moved by one ulp (ulp_samples random moves)."""
-    ref = oracle.solve(oracle.Problem.from_instance(inst), lam1, lam2, **kw)
-    runs = [(oracle.solve(_reversed(inst), lam1, lam2, **kw), True)]
-    rng = np.random.default_rng(7)
-    for _ in range(ulp_samples):
-        y2 = inst.y + np.spacing(inst.y) * rng.choice([-1.0, 1.0], size=inst.n)
-        runs.append((oracle.solve(oracle.Problem(inst.X, inst.dtype, y2, inst.edges), lam1, lam2, **kw), False))
-    scale = max(np.max(np.abs(ref.beta)), 1e-300)
-    ref.spread = 0.0
-    for r, rev in runs:
-        assert r.mm_iters == ref.mm_iters
-        ref.spread = max(ref.spread, float(np.max(np.abs((r.beta[::-1] if rev else r.beta) - ref.beta)) / scale))
-    return ref
 
 
 class _Sol:
