@@ -105,7 +105,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "paper"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--method", default="pcg", choices=["pcg", "cholesky"],
                     help="c1: Algorithm 2 (PCG) or Algorithm 1 (dense Cholesky per MM iteration)")
@@ -128,6 +128,11 @@ def main():
     ap.add_argument("--serve-instances", type=int, default=1, help="resident problems per (p, graph) cell")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0)
     ap.add_argument("--serve-ps", default="1000,5000,10000,50000")
+    ap.add_argument("--paper-scenarios", default="C1,C2,C3,C4", help="paper: scenarios of sections 5.1/5.2")
+    ap.add_argument("--paper-sizes", default="", help="paper: sizes to run (p, or q for C4); default all four")
+    ap.add_argument("--paper-datasets", type=int, default=10, help="paper: data sets per scenario and size")
+    ap.add_argument("--paper-first", type=int, default=0, help="paper: index of the first data set")
+    ap.add_argument("--paper-inner", type=float, default=0.0, help="paper: inner tolerance (0: equal to 1e-5)")
     ap.add_argument("--serve-tol", type=float, default=1e-6)
     ap.add_argument("--serve-allpairs", default="pcg", choices=["pcg", "cholesky"],
                     help="c5: method for the all-pairs requests (PCG or Algorithm 1's dense Cholesky)")
@@ -147,6 +152,8 @@ def main():
         return serve_main(args, flr)
     if args.workload == "c3":
         return grid_main(args, flr)
+    if args.workload == "paper":
+        return paper_main(args, flr)
     if args.method == "cholesky":
         return dense_main(args, flr)
     inst, wname = make_workload(args.workload)
@@ -305,6 +312,81 @@ def dense_main(args, flr):
                                           % (r.mm_iters, dt, r.threads)}
     prob.close()
     ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+def paper_main(args, flr):
+    """The paper's simulation scenarios (section 5.1: C1-C3 on a chain; 5.2:
+    C4 on a lattice) at their sizes, ten data sets each, the four
+    (lambda1, lambda2) settings, relative objective change 1e-5 and eps 1e-8,
+    every solve from the method's own start.  Per cell: the mean and spread
+    of the MM iteration counts and the GPU seconds per solve, beside the
+    paper's MM and MMGPU columns (Tables C.1-C.4, other hardware: context)."""
+    import numpy as np
+
+    import flrgen
+
+    printed = {(c["scenario"], c["size"], c["lambda1"], c["lambda2"]): c
+               for c in json.load(open(os.path.join(ROOT, "tests", "golden", "paper_tables_c.json")))["cells"]}
+    ctx = flr.Context(0)
+    cells, t_all, n_all = [], 0.0, 0
+    for sc in args.paper_scenarios.split(","):
+        sizes = [int(x) for x in args.paper_sizes.split(",")] if args.paper_sizes else flrgen.PAPER_SIZES[sc]
+        for size in sizes:
+            rec = {lp: {"mm": [], "cg": [], "sec": [], "status": []} for lp in flrgen.PAPER_LAMBDAS}
+            for d in range(args.paper_first, args.paper_first + args.paper_datasets):
+                inst = flrgen.paper_scenario(sc, size, d)
+                prob = flr.Problem.from_instance(ctx, inst)
+                for lp in flrgen.PAPER_LAMBDAS:
+                    t0 = time.perf_counter()
+                    s = prob.solve(lp[0], lp[1], tol=flrgen.PAPER_TOL, eps=1e-8, inner_tol=args.paper_inner)
+                    dt = time.perf_counter() - t0
+                    r = rec[lp]
+                    r["mm"].append(s.mm_iters)
+                    r["cg"].append(s.cg_iters)
+                    r["sec"].append(dt)
+                    r["status"].append(s.status)
+                    t_all += dt
+                    n_all += 1
+                prob.close()
+                print("bench: %s size %d data set %d: MM %s" % (sc, size, d, [rec[lp]["mm"][-1] for lp in
+                                                                              flrgen.PAPER_LAMBDAS]),
+                      file=sys.stderr, flush=True)
+            for lp in flrgen.PAPER_LAMBDAS:
+                r, pc = rec[lp], printed.get((sc, size, lp[0], lp[1]), {})
+                mm = np.array(r["mm"], dtype=float)
+                cells.append({"scenario": sc, "size": size, "p": size * size if sc == "C4" else size,
+                              "lambda1": lp[0], "lambda2": lp[1], "mm_mean": float(mm.mean()),
+                              "mm_sd": float(mm.std(ddof=1)) if mm.size > 1 else 0.0,
+                              "mm_min": int(mm.min()), "mm_max": int(mm.max()), "mm_all": [int(x) for x in mm],
+                              "cg_mean": float(np.mean(r["cg"])), "gpu_seconds_mean": float(np.mean(r["sec"])),
+                              "all_ok": all(x == flr.FLR_OK for x in r["status"]),
+                              "paper_mm_iters": pc.get("mm_iters"), "paper_mm_seconds": pc.get("mm_seconds"),
+                              "paper_mmgpu_iters": pc.get("mmgpu_iters"), "paper_mmgpu_seconds": pc.get("mmgpu_seconds")})
+                c = cells[-1]
+                print("bench: %s size %d lam (%g, %g): MM %.1f +- %.1f (paper MM %s), GPU %.4f s (paper MMGPU %s s, "
+                      "MM %s s)" % (sc, size, lp[0], lp[1], c["mm_mean"], c["mm_sd"], c["paper_mm_iters"],
+                                    c["gpu_seconds_mean"], c["paper_mmgpu_seconds"], c["paper_mm_seconds"]),
+                      file=sys.stderr, flush=True)
+    ctx.close()
+    line = {
+        "metric": "paper scenarios C1-C4 (sections 5.1, 5.2): MM iterations and GPU seconds per solve vs Tables C.1-C.4",
+        "value": n_all / t_all,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": n_all,
+        "warmup": 0,
+        "ms_per_step": 1000.0 * t_all / n_all,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "paper_scenarios_%s" % args.paper_scenarios.replace(",", ""), "n": flrgen.PAPER_N,
+                   "datasets": args.paper_datasets, "first_dataset": args.paper_first, "tol": flrgen.PAPER_TOL, "eps": 1e-8,
+                   "inner_tol": args.paper_inner or flrgen.PAPER_TOL, "x_storage": "f64"},
+        "cells": cells,
+    }
     print(json.dumps(line), flush=True)
 
 

@@ -350,6 +350,65 @@ def serving_requests(nreq: int, seed: int = 5, rate: float = 1.0, ps=SERVE_PS):
     return out
 
 
+# ----------------------------------------------------------------------------
+# the paper's simulation scenarios: section 5.1 (C1-C3, chain) and 5.2 (C4, lattice)
+# ----------------------------------------------------------------------------
+PAPER_LAMBDAS = ((0.1, 0.1), (0.1, 1.0), (1.0, 0.1), (1.0, 1.0))  # both sections' four settings
+PAPER_TOL = 1e-5     # relative objective change at which every algorithm stops (section 5)
+PAPER_N = 1000
+PAPER_SIZES = {"C1": (200, 1000, 10000, 20000), "C2": (200, 1000, 10000, 20000),
+               "C3": (200, 1000, 10000, 20000), "C4": (16, 32, 64, 128)}  # p, or the lattice side q for C4
+_PAPER_IDS = {"C1": 1, "C2": 2, "C3": 3, "C4": 4}
+
+
+def paper_beta(scenario: str, size: int) -> np.ndarray:
+    """True coefficients of the scenario (section 5.1 for C1-C3, indices
+    there are 1-based; section 5.2 for C4, where size is the side q and beta =
+    vec(B) of the q x q block pattern)."""
+    if scenario == "C1":  # sparse: 41 nonzeros at fixed positions
+        b = np.zeros(size)
+        b[0:20] = 2.0
+        b[120:125] = 2.0
+        b[40] = 3.0
+        b[70:85] = 1.0
+        return b
+    if scenario == "C2":  # moderately sparse: 30 % nonzero
+        assert size % 10 == 0
+        b = np.zeros(size)
+        b[size // 10:2 * size // 10] = 1.0
+        b[2 * size // 10:4 * size // 10] = 2.0
+        return b
+    if scenario == "C3":  # dense: +1 on the first half, -1 on the second
+        assert size % 2 == 0
+        return np.where(np.arange(size) < size // 2, 1.0, -1.0)
+    if scenario == "C4":  # q x q: +2 on the four diagonal blocks of side q/4, -2 on the anti-diagonal ones
+        q = size
+        assert q % 4 == 0
+        h = q // 4
+        B = np.zeros((q, q))
+        for k in range(4):
+            B[k * h:(k + 1) * h, k * h:(k + 1) * h] = 2.0
+            B[k * h:(k + 1) * h, (3 - k) * h:(4 - k) * h] = -2.0
+        return B.ravel(order="F").copy()
+    raise ValueError(scenario)
+
+
+def paper_scenario(scenario: str, size: int, dataset: int, n: int = PAPER_N) -> Instance:
+    """Data set `dataset` (0..9 in the paper) of a scenario: X rows iid
+    N(0, I_p) in FP64, y = X beta + N(0, I_n) (the generating equation of
+    section 5.1), chain edges for C1-C3 and the q x q lattice for C4;
+    tolerance 1e-5, eps 1e-8 (section 5).  lam1/lam2 hold the first of the
+    four settings; a caller solves all four on the same data set."""
+    p = size * size if scenario == "C4" else size
+    graph = "lattice" if scenario == "C4" else "chain"
+    seed = [1306, _PAPER_IDS[scenario], size, dataset]
+    beta = paper_beta(scenario, size)
+    l1, l2 = PAPER_LAMBDAS[0]
+    return make_instance("paper_%s_%d_d%d" % (scenario, size, dataset), n, p, graph, F64, lambda r: beta,
+                         lambda r: gaussian_x(n, p, r, F64), 1.0, seed, l1, l2, tol=PAPER_TOL,
+                         q=size if scenario == "C4" else None)
+
+
 def small_instance(n: int, p: int, graph: str = "chain", dtype: int = F64, seed: int = 11,
                    lam1: float = 0.1, lam2: float = 0.5, q=None, sigma: float = 1.0,
                    x_kind: str = "gauss") -> Instance:
