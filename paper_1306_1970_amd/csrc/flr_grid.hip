@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -728,20 +729,75 @@ static flr_status grid_run(flr_problem h, GridWork* gw, GridHost hb, const doubl
     if (e != hipSuccess) return e;
     return gw->ev ? hipEventRecord(gw->ev, h->stream) : hipStreamSynchronize(h->stream);
   };
+  // One batched step: the two products (and the split-K sum) for the active
+  // columns, then the fused per-column kernel.
+  auto one_step = [&](int64_t st) -> hipError_t {
+    hipError_t e = grid_products(h, *gw, G, G.O, nact);
+    if (e != hipSuccess) return e;
+    const int hold = hold_period > 1 && nact >= kHoldMinCols && st % hold_period != 0 ? 1 : 0;
+    if (P.band)
+      hipLaunchKernelGGL(k_col<true>, dim3((unsigned)nact), dim3(kWG), 0, h->stream, G, hold);
+    else
+      hipLaunchKernelGGL(k_col<false>, dim3((unsigned)nact), dim3(kWG), 0, h->stream, G, hold);
+    return hipGetLastError();
+  };
+  // The allocating entry point replays whole polling periods (check_every
+  // steps) as HIP graphs, one per hold pattern of the period, captured for the
+  // current set of active columns and operand buffer and captured again after
+  // a compaction.  The no-allocation entry point (no event) launches eagerly,
+  // since instantiating a graph may allocate; FLR_GRID_GRAPH=0 does the same.
+  const char* gv = std::getenv("FLR_GRID_GRAPH");
+  const bool use_graphs = gw->ev && !(gv && gv[0] == '0');
+  struct Period {
+    unsigned mask;
+    hipGraphExec_t exec;
+  };
+  std::vector<Period> graphs;
+  auto drop_graphs = [&]() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+  };
+  struct GraphGuard {
+    std::function<void()> f;
+    ~GraphGuard() { f(); }
+  } guard{drop_graphs};
+  auto run_period = [&](int64_t st) -> hipError_t {
+    unsigned mask = 0;
+    for (int k = 0; k < check_every; ++k)
+      if (hold_period > 1 && nact >= kHoldMinCols && (st + k) % hold_period != 0) mask |= 1u << k;
+    for (auto& g : graphs)
+      if (g.mask == mask) return hipGraphLaunch(g.exec, h->stream);
+    hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t body = hipSuccess;
+    for (int k = 0; k < check_every && body == hipSuccess; ++k) body = one_step(st + k);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(h->stream, &graph);
+    if (body != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return body;
+    }
+    if (e != hipSuccess) return e;
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return e;
+    graphs.push_back({mask, exec});
+    return hipGraphLaunch(exec, h->stream);
+  };
   while (!done) {
     if (step >= max_steps) return gfail(FLR_ERR_DEVICE, "grid solve did not terminate within its step bound");
     if (progress && std::chrono::steady_clock::now() - t_prog > std::chrono::seconds(5)) {
       t_prog = std::chrono::steady_clock::now();
       std::fprintf(stderr, "flr grid: %lld batched steps, %d of %d columns active\n", (long long)step, nact, B);
     }
-    GCK(grid_products(h, *gw, G, G.O, nact));
-    const int hold = hold_period > 1 && nact >= kHoldMinCols && step % hold_period != 0 ? 1 : 0;
-    if (P.band)
-      hipLaunchKernelGGL(k_col<true>, dim3((unsigned)nact), dim3(kWG), 0, h->stream, G, hold);
-    else
-      hipLaunchKernelGGL(k_col<false>, dim3((unsigned)nact), dim3(kWG), 0, h->stream, G, hold);
-    GCK(hipGetLastError());
-    ++step;
+    if (use_graphs && step % check_every == 0) {
+      GCK(run_period(step));
+      step += check_every;
+    } else {
+      GCK(one_step(step));
+      ++step;
+    }
     if (step % check_every == 0) {
       if (pending) {
         if (gw->ev) GCK(hipEventSynchronize(gw->ev));
@@ -775,6 +831,7 @@ static flr_status grid_run(flr_problem h, GridWork* gw, GridHost hb, const doubl
             std::swap(G.O, Ospare);
             std::swap(hb.act, hb.nxt);
             nact = cnt;
+            drop_graphs();  // captured for the old columns and operand buffer
           }
           pending = false;
           continue;

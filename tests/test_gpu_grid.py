@@ -203,6 +203,35 @@ def test_grid_lattice_held_boundaries(flr, ctx, monkeypatch):
         assert err <= 1e-8 and err1 <= 1e-10
 
 
+@pytest.mark.parametrize("graph,vals", [("chain", np.logspace(-2.0, 0.8, 7)), ("lattice", np.array([0.1, 0.6, 2.0]))])
+def test_grid_graph_replay_matches_eager(flr, ctx, monkeypatch, graph, vals):
+    # The allocating grid replays each polling period (8 batched steps) as a HIP graph, one per hold
+    # pattern, captured again after every compaction.  The same solve with eager launches
+    # (FLR_GRID_GRAPH=0) must give the same bits, and so must a second graph solve on the same handle
+    # after eager work in between: every replay is checked against eager arithmetic.
+    inst = flrgen.small_instance(40 if graph == "chain" else 80, 200 if graph == "chain" else 144, graph,
+                                 dtype=flrgen.F64, seed=34 if graph == "chain" else 36)
+    l1, l2 = flrgen.grid_lambdas(vals)
+    l1, l2 = l1[:48], l2[:48]
+    prob = flr.Problem.from_instance(ctx, inst)
+    st_g, beta_g, res_g = prob.solve_grid(l1, l2, tol=1e-9, inner_tol=INNER)
+    monkeypatch.setenv("FLR_GRID_GRAPH", "0")
+    st_e, beta_e, res_e = prob.solve_grid(l1, l2, tol=1e-9, inner_tol=INNER)
+    single = prob.solve(l1[0], l2[0], tol=1e-9, inner_tol=INNER)  # other eager work on the handle
+    monkeypatch.delenv("FLR_GRID_GRAPH")
+    st_g2, beta_g2, res_g2 = prob.solve_grid(l1, l2, tol=1e-9, inner_tol=INNER)
+    prob.close()
+    mms = [r["mm_iters"] for r in res_g]
+    print("  %s: %d columns, MM %d..%d, PCG steps up to %d" % (graph, l1.size, min(mms), max(mms),
+                                                              max(r["cg_iters"] for r in res_g)), flush=True)
+    assert st_g == st_e == st_g2 == flr.FLR_OK
+    assert np.array_equal(beta_g, beta_e) and np.array_equal(beta_g2, beta_e)
+    for a, b, c in zip(res_g, res_e, res_g2):
+        assert (a["mm_iters"], a["cg_iters"], a["objective"]) == (b["mm_iters"], b["cg_iters"], b["objective"])
+        assert (c["mm_iters"], c["cg_iters"], c["objective"]) == (b["mm_iters"], b["cg_iters"], b["objective"])
+    assert single.mm_iters == res_e[0]["mm_iters"]
+
+
 def test_grid_workspace_is_charged_to_footprint(flr, ctx):
     # serving admission charges flr_problem_footprint: the grid workspace a handle keeps after a
     # grid solve (per-column vectors, products, band factors) must be part of it
