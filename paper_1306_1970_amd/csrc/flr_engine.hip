@@ -22,6 +22,9 @@ hipError_t launch_rotation(const Dims& D, const Bufs& B, int par, int which, hip
 hipError_t launch_setup(const Dims& D, const void* X, const double* y, double* cpart, double* spart, double* c,
                         double* s, hipStream_t st);
 hipError_t launch_init(const Dims& D, const Bufs& B, const double* warm, int use_warm, hipStream_t st);
+hipError_t launch_grouped(int dtype, bool mixed, const GroupEntry* e, int count, int wgs, int par, int which,
+                          hipStream_t st);
+hipError_t launch_gather_states(const GroupEntry* e, int count, State* out, hipStream_t st);
 hipError_t launch_check_finite(const void* X, int dtype, int64_t count, int* flag, hipStream_t st);
 }  // namespace flr
 
@@ -144,8 +147,9 @@ struct SolveRun {
   std::chrono::steady_clock::time_point t0;
 };
 
-// Parameters, warm start, initial state and the captured rotation of a solve.
-flr_status solve_begin(flr_problem h, double l1, double l2, double tol, const flr_solve_opts* o, SolveRun& run) {
+// Parameters, warm start and initial state of a solve (solve_begin adds the
+// captured rotation; the ragged batch captures grouped launches instead).
+flr_status solve_prepare(flr_problem h, double l1, double l2, double tol, const flr_solve_opts* o, SolveRun& run) {
   run.t0 = std::chrono::steady_clock::now();
   run.h = h;
   flr_solve_opts dflt;
@@ -192,11 +196,6 @@ flr_status solve_begin(flr_problem h, double l1, double l2, double tol, const fl
     use_warm = 1;
   }
   HIP_OR_FAIL(launch_init(D, h->B, warm, use_warm, h->stream));
-  const bool mixed = P.mixed != 0;
-  const bool band = P.band != 0;
-  flr_status gs = build_graph(h, mixed, band);
-  if (gs != FLR_OK) return gs;
-  run.gexec = h->gexec[mixed][band];
   // every MM step takes at most max_cg PCG steps, as many FP64 residual
   // refreshes (mixed precision: each follows at least one PCG step) and its
   // boundary; one graph launch holds kRounds rotations
@@ -204,6 +203,17 @@ flr_status solve_begin(flr_problem h, double l1, double l2, double tol, const fl
   run.launched = 0;
   run.in_flight = 0;
   run.done = false;
+  return FLR_OK;
+}
+
+flr_status solve_begin(flr_problem h, double l1, double l2, double tol, const flr_solve_opts* o, SolveRun& run) {
+  flr_status st = solve_prepare(h, l1, l2, tol, o, run);
+  if (st != FLR_OK) return st;
+  const bool mixed = h->h_prm->mixed != 0;
+  const bool band = h->h_prm->band != 0;
+  st = build_graph(h, mixed, band);
+  if (st != FLR_OK) return st;
+  run.gexec = h->gexec[mixed][band];
   return FLR_OK;
 }
 
@@ -289,6 +299,117 @@ flr_status run_solve(flr_problem h, double l1, double l2, double tol, const flr_
     }
   }
   return solve_end(run, beta_out, res);
+}
+
+// Device and host buffers of one ragged batch (released on every return).
+struct BatchWork {
+  GroupEntry* d_ent = nullptr;
+  State* d_st = nullptr;
+  State* h_st = nullptr;      // pinned, 2 slots of count states; the last states read are at h_st
+  State* h_slot[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~BatchWork() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (auto e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (h_st) (void)hipHostFree(h_st);
+    if (d_ent) (void)hipFree(d_ent);
+  }
+};
+
+// The ragged batch in grouped launches: the problems are sorted into groups
+// of one stored type and precision; one round is, per group, one launch each
+// of A, B and C over every problem of the group and one banded-solve launch
+// (the problems without a band only pass their state on, which keeps every
+// problem's state parity that of the banded rotation).  kRounds rounds are
+// captured in one graph on the first problem's stream and launched with two
+// in flight, the states of all problems gathered into one copy per launch;
+// the batch ends when every problem's state says done.
+flr_status batch_run(const flr_problem* hs, int32_t count, std::vector<SolveRun>& runs, BatchWork& bw) {
+  struct Group {
+    int dtype;
+    bool mixed;
+    int first, count, wa, wb, wc;
+  };
+  std::vector<GroupEntry> ents;
+  std::vector<Group> groups;
+  std::vector<int> order;  // problem index of each entry
+  int64_t max_launches = 0;
+  for (int dt = 0; dt < 3; ++dt) {
+    for (int mx = 0; mx < 2; ++mx) {
+      Group g{dt, mx != 0, (int)ents.size(), 0, 0, 0, 0};
+      for (int32_t i = 0; i < count; ++i) {
+        flr_problem h = hs[i];
+        if (h->D.dtype != dt || (h->h_prm->mixed != 0) != (mx != 0)) continue;
+        GroupEntry e{};
+        e.D = h->D;
+        e.B = h->B;
+        e.wg_a = g.wa;
+        e.wg_b = g.wb;
+        e.wg_c = g.wc;
+        e.band = h->h_prm->band != 0 ? 1 : 0;
+        g.wa += h->D.cb1 * h->D.rb1;
+        g.wb += h->D.gridB;
+        g.wc += h->D.nblk;
+        ents.push_back(e);
+        order.push_back(i);
+        ++g.count;
+        max_launches = std::max(max_launches, runs[(size_t)i].max_launches);
+      }
+      if (g.count) groups.push_back(g);
+    }
+  }
+  // states are gathered in entry order
+  const size_t nst = (size_t)count;
+  HIP_OR_FAIL(hipMalloc(reinterpret_cast<void**>(&bw.d_ent), ents.size() * sizeof(GroupEntry) + nst * sizeof(State)));
+  bw.d_st = reinterpret_cast<State*>(bw.d_ent + ents.size());
+  HIP_OR_FAIL(hipHostMalloc(reinterpret_cast<void**>(&bw.h_st), 3 * nst * sizeof(State), hipHostMallocDefault));
+  bw.h_slot[0] = bw.h_st + nst;
+  bw.h_slot[1] = bw.h_st + 2 * nst;
+  for (auto& e : bw.ev) HIP_OR_FAIL(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  hipStream_t st = hs[0]->stream;
+  // the problems' initializations (on their own streams) come first
+  for (int32_t i = 0; i < count; ++i) HIP_OR_FAIL(hipStreamSynchronize(hs[i]->stream));
+  HIP_OR_FAIL(hipMemcpy(bw.d_ent, ents.data(), ents.size() * sizeof(GroupEntry), hipMemcpyHostToDevice));
+  HIP_OR_FAIL(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  hipError_t err = hipSuccess;
+  for (int r = 0; r < kRounds && err == hipSuccess; ++r)
+    for (const Group& g : groups)
+      for (int which = 0; which < 4 && err == hipSuccess; ++which) {
+        const int wgs = which == 0 ? g.wa : which == 1 ? g.wb : which == 2 ? g.wc : g.count;
+        err = launch_grouped(g.dtype, g.mixed, bw.d_ent + g.first, g.count, wgs, which & 1, which, st);
+      }
+  hipError_t e2 = hipStreamEndCapture(st, &bw.graph);
+  if (err != hipSuccess) return fail(FLR_ERR_DEVICE, std::string("batch capture: ") + hipGetErrorString(err));
+  HIP_OR_FAIL(e2);
+  HIP_OR_FAIL(hipGraphInstantiate(&bw.exec, bw.graph, nullptr, nullptr, 0));
+  int64_t launched = 0;
+  int in_flight = 0;
+  bool done = false;
+  while (!done) {
+    if (in_flight < 2) {
+      if (launched >= max_launches) return fail(FLR_ERR_DEVICE, "batch did not terminate within its launch bound");
+      const int slot = (int)(launched & 1);
+      HIP_OR_FAIL(hipGraphLaunch(bw.exec, st));
+      HIP_OR_FAIL(launch_gather_states(bw.d_ent, (int)ents.size(), bw.d_st, st));
+      HIP_OR_FAIL(hipMemcpyAsync(bw.h_slot[slot], bw.d_st, nst * sizeof(State), hipMemcpyDeviceToHost, st));
+      HIP_OR_FAIL(hipEventRecord(bw.ev[slot], st));
+      ++launched;
+      if (++in_flight < 2) continue;
+    }
+    const int oldest = (int)((launched - in_flight) & 1);
+    HIP_OR_FAIL(hipEventSynchronize(bw.ev[oldest]));
+    --in_flight;
+    done = true;
+    for (size_t k = 0; k < nst; ++k) done = done && bw.h_slot[oldest][k].phase == PH_DONE;
+  }
+  HIP_OR_FAIL(hipStreamSynchronize(st));
+  const State* last = bw.h_slot[(launched - 1) & 1];
+  for (size_t k = 0; k < nst; ++k) bw.h_st[order[k]] = last[k];
+  return FLR_OK;
 }
 
 }  // namespace
@@ -619,45 +740,36 @@ flr_status flr_solve_batch(const flr_problem* hs, int32_t count, const double* l
     return fail(FLR_ERR_INVALID_ARG, "flr_solve_batch runs Algorithm 2 (PCG) only");
   std::vector<SolveRun> runs((size_t)count);
   for (int32_t i = 0; i < count; ++i) {
-    flr_status st = solve_begin(hs[i], l1[i], l2[i], tol, opts, runs[(size_t)i]);
+    flr_status st = solve_prepare(hs[i], l1[i], l2[i], tol, opts, runs[(size_t)i]);
     if (st != FLR_OK) {
       for (int32_t k = 0; k < i; ++k) (void)hipStreamSynchronize(hs[k]->stream);
       return st;
     }
   }
-  // one host thread keeps every solve's rotation in flight on its own stream
-  int32_t left = count;
-  while (left > 0) {
-    bool any = false;
-    left = 0;
-    for (auto& run : runs) {
-      if (run.done) continue;
-      bool moved = false;
-      flr_status st = solve_advance(run, false, &moved);
-      if (st != FLR_OK) {
-        for (auto& r2 : runs) (void)hipStreamSynchronize(r2.h->stream);
-        return st;
-      }
-      any = any || moved;
-      if (!run.done) ++left;
-    }
-    if (!any && left > 0) {  // nothing retired this pass: wait for the first unfinished solve's older launch
-      for (auto& run : runs) {
-        if (run.done) continue;
-        bool moved = false;
-        flr_status st = solve_advance(run, true, &moved);
-        if (st != FLR_OK) {
-          for (auto& r2 : runs) (void)hipStreamSynchronize(r2.h->stream);
-          return st;
-        }
-        break;
-      }
-    }
-  }
+  BatchWork bw;
+  flr_status st = batch_run(hs, count, runs, bw);
+  for (int32_t i = 0; i < count; ++i) (void)hipStreamSynchronize(hs[i]->stream);
+  if (st != FLR_OK) return st;
   flr_status first = FLR_OK;
   for (int32_t i = 0; i < count; ++i) {
-    flr_status st = solve_end(runs[(size_t)i], beta_out ? beta_out[i] : nullptr, res ? &res[i] : nullptr);
-    if (st != FLR_OK && first == FLR_OK) first = st;
+    flr_problem h = hs[i];
+    const State fin = bw.h_st[i];
+    if (beta_out && beta_out[i]) HIP_OR_FAIL(hipMemcpy(beta_out[i], h->B.x, h->D.p * sizeof(double), hipMemcpyDefault));
+    h->has_solution = true;
+    const flr_status si = fin.status == ST_OK ? FLR_OK : fin.status == ST_MAX_ITER ? FLR_ERR_MAX_ITER : FLR_ERR_NUMERICAL;
+    if (res) {
+      res[i].objective = fin.f_new;
+      res[i].rel_change = fin.rel_change;
+      res[i].rel_residual = fin.rel_res;
+      res[i].cg_iters = fin.cg_total;
+      res[i].mm_iters = fin.mm_iter;
+      res[i].status = si;
+      res[i].seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - runs[(size_t)i].t0).count();
+    }
+    if (si != FLR_OK && first == FLR_OK) {
+      first = si;
+      g_last_error = si == FLR_ERR_MAX_ITER ? "MM iteration cap reached" : "non-finite value or CG breakdown inside the solve";
+    }
   }
   return first;
 }

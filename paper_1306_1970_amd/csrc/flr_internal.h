@@ -115,4 +115,15 @@ struct Bufs {
   const Params* prm;
 };
 
+// One problem of a grouped launch (the ragged batch): its sizes and buffers,
+// the first workgroup of its share of the grouped A, B and C launches, and
+// whether its M is applied through the banded factor (one workgroup of the
+// grouped band launch; the other problems' workgroup only passes the state on).
+struct GroupEntry {
+  Dims D;
+  Bufs B;
+  int32_t wg_a, wg_b, wg_c;
+  int32_t band;
+};
+
 }  // namespace flr

@@ -166,14 +166,14 @@ __device__ inline void rows_a(const Dims& D, const Bufs& B, const XT* Xb, int cb
 // pointer (scalar loads), so it does not wait behind the X loads.
 // ---------------------------------------------------------------------------
 template <typename XT, bool MX>
-__global__ __launch_bounds__(kWG) void k_gemv_a(Dims D, Bufs B, const State* __restrict__ sin,
-                                                State* __restrict__ sout) {
+__device__ __forceinline__ void gemv_a_body(const Dims& D, const Bufs& B, const State* __restrict__ sin,
+                                            State* __restrict__ sout, const int wg) {
   constexpr int V = XV<XT>::V;
   constexpr int NV = 4;  // 16-byte loads per lane per row (the panel is 256 V columns)
   using RAW = typename XV<XT>::raw;
   const State s = *sin;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wg = blockIdx.x, cb = wg % D.cb1, rb = wg / D.cb1;
+  const int cb = wg % D.cb1, rb = wg / D.cb1;
   if (wg == 0 && tid == 0) *sout = s;
   if (s.phase == PH_DONE) return;
   const int64_t c0 = (int64_t)cb * D.c1;
@@ -236,6 +236,12 @@ __global__ __launch_bounds__(kWG) void k_gemv_a(Dims D, Bufs B, const State* __r
     rows_a<XT, double>(D, B, Xb, cb, r0, r1, c0, lane, wave, sh_v, cur0, cur1);
 }
 
+template <typename XT, bool MX>
+__global__ __launch_bounds__(kWG) void k_gemv_a(Dims D, Bufs B, const State* __restrict__ sin,
+                                                State* __restrict__ sout) {
+  gemv_a_body<XT, MX>(D, B, sin, sout, blockIdx.x);
+}
+
 // (M v)_j = lambda1 a_j v_j + lambda2 sum_k w_jk (v_j - v_k)  (A and B of the linear system)
 __device__ inline double apply_m(const Bufs& B, const Params& prm, int64_t j, const double* v) {
   const double vj = v[j];
@@ -288,13 +294,14 @@ __device__ inline void cols_b(const Dims& D, const XT* Xb, int64_t r0, int64_t r
 // the penalty sums of f, and each block's factorization product.
 // ---------------------------------------------------------------------------
 template <typename XT, bool MX>
-__global__ __launch_bounds__(kWG) void k_gemv_b(Dims D, Bufs B, const State* __restrict__ sin,
-                                                State* __restrict__ sout, const Params* __restrict__ prmp) {
+__device__ __forceinline__ void gemv_b_body(const Dims& D, const Bufs& B, const State* __restrict__ sin,
+                                            State* __restrict__ sout, const Params* __restrict__ prmp,
+                                            const int wg) {
   constexpr int V = XV<XT>::V;
   constexpr int RU = 8;  // rows per wave in flight
   using RAW = typename XV<XT>::raw;
   const State s = *sin;
-  const int wg = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   if (wg == 0 && tid == 0) *sout = s;
   if (s.phase == PH_DONE) return;
   const int lane = tid & 63, wave = tid >> 6;
@@ -444,6 +451,12 @@ __global__ __launch_bounds__(kWG) void k_gemv_b(Dims D, Bufs B, const State* __r
       if (tid == 0) B.counter[16] = 0u;
     }
   }
+}
+
+template <typename XT, bool MX>
+__global__ __launch_bounds__(kWG) void k_gemv_b(Dims D, Bufs B, const State* __restrict__ sin,
+                                                State* __restrict__ sout, const Params* __restrict__ prmp) {
+  gemv_b_body<XT, MX>(D, B, sin, sout, prmp, blockIdx.x);
 }
 
 // Zero-inflow local solve of the block for the current residual r_j and the
@@ -704,11 +717,12 @@ __device__ inline bool arrive_last(const Bufs& B, int nblocks, int* flag) {
 // block's own continued fraction), the gain vectors, r0 = c - Q x0 and its
 // local solve.  The last workgroup to finish combines the blocks.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kWG) void k_block(Dims D, Bufs B, const State* __restrict__ sin,
-                                               State* __restrict__ sout, const Params* __restrict__ prmp) {
+__device__ __forceinline__ void block_body(const Dims& D, const Bufs& B, const State* __restrict__ sin,
+                                           State* __restrict__ sout, const Params* __restrict__ prmp,
+                                           const int b) {
   constexpr int QMAX = 16;  // row panels whose partial products are prefetched
   const State s = *sin;
-  const int b = blockIdx.x, tid = threadIdx.x;
+  const int tid = threadIdx.x;
   if (s.phase == PH_DONE) {
     if (b == 0 && tid == 0) *sout = s;
     return;
@@ -920,14 +934,19 @@ __global__ __launch_bounds__(kWG) void k_block(Dims D, Bufs B, const State* __re
   }
 }
 
+__global__ __launch_bounds__(kWG) void k_block(Dims D, Bufs B, const State* __restrict__ sin,
+                                               State* __restrict__ sout, const Params* __restrict__ prmp) {
+  block_body(D, B, sin, sout, prmp, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // K (banded M, one workgroup): z = M^-1 r through the banded Cholesky factor,
 // r^T z, ||r||, the inner stopping test of Algorithm 2 and gamma.  After an
 // MM boundary (PH_BANDMM) it first assembles M from the new weights and
 // factors it.  A then rebuilds p from z = yv (gains and carries are zero).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kWG) void k_band(Dims D, Bufs B, const State* __restrict__ sin,
-                                              State* __restrict__ sout, const Params* __restrict__ prmp) {
+__device__ __forceinline__ void band_body(const Dims& D, const Bufs& B, const State* __restrict__ sin,
+                                          State* __restrict__ sout, const Params* __restrict__ prmp) {
   __shared__ double lds[kBandLds];
   __shared__ double red[24];
   const State s = *sin;
@@ -972,9 +991,93 @@ __global__ __launch_bounds__(kWG) void k_band(Dims D, Bufs B, const State* __res
   }
 }
 
+__global__ __launch_bounds__(kWG) void k_band(Dims D, Bufs B, const State* __restrict__ sin,
+                                              State* __restrict__ sout, const Params* __restrict__ prmp) {
+  band_body(D, B, sin, sout, prmp);
+}
+
 // ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Grouped launches of the ragged batch: one launch of each rotation kernel
+// covers every problem of the batch that stores X in the same type; a
+// workgroup finds its problem from the offsets of the problems' shares and
+// runs that problem's kernel body on its own operands, so each problem's
+// arithmetic is that of its solo launch.
+// ---------------------------------------------------------------------------
+__device__ inline int group_of(const GroupEntry* __restrict__ e, int count, int wg, int which) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int start = which == 0 ? e[mid].wg_a : which == 1 ? e[mid].wg_b : e[mid].wg_c;
+    if (start <= wg) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename XT, bool MX>
+__global__ __launch_bounds__(kWG) void k_gemv_a_grp(const GroupEntry* __restrict__ e, int count, int par) {
+  const GroupEntry& g = e[group_of(e, count, (int)blockIdx.x, 0)];
+  gemv_a_body<XT, MX>(g.D, g.B, g.B.st + par, g.B.st + (par ^ 1), (int)blockIdx.x - g.wg_a);
+}
+
+template <typename XT, bool MX>
+__global__ __launch_bounds__(kWG) void k_gemv_b_grp(const GroupEntry* __restrict__ e, int count, int par) {
+  const GroupEntry& g = e[group_of(e, count, (int)blockIdx.x, 1)];
+  gemv_b_body<XT, MX>(g.D, g.B, g.B.st + par, g.B.st + (par ^ 1), g.B.prm, (int)blockIdx.x - g.wg_b);
+}
+
+__global__ __launch_bounds__(kWG) void k_block_grp(const GroupEntry* __restrict__ e, int count, int par) {
+  const GroupEntry& g = e[group_of(e, count, (int)blockIdx.x, 2)];
+  block_body(g.D, g.B, g.B.st + par, g.B.st + (par ^ 1), g.B.prm, (int)blockIdx.x - g.wg_c);
+}
+
+__global__ __launch_bounds__(kWG) void k_band_grp(const GroupEntry* __restrict__ e, int par) {
+  const GroupEntry& g = e[blockIdx.x];
+  if (!g.band) {
+    if (threadIdx.x == 0) g.B.st[par ^ 1] = g.B.st[par];
+    return;
+  }
+  band_body(g.D, g.B, g.B.st + par, g.B.st + (par ^ 1), g.B.prm);
+}
+
+// State of every problem of a batch after a graph launch (slot 0 of each).
+__global__ __launch_bounds__(kWG) void k_gather_states(const GroupEntry* __restrict__ e, int count,
+                                                       State* __restrict__ out) {
+  const int i = (int)blockIdx.x * kWG + threadIdx.x;
+  if (i < count) out[i] = e[i].B.st[0];
+}
+
+template <typename XT, bool MX>
+static hipError_t launch_grouped_t(const GroupEntry* e, int count, int wgs, int par, int which, hipStream_t st) {
+  switch (which) {
+    case 0: hipLaunchKernelGGL((k_gemv_a_grp<XT, MX>), dim3(wgs), dim3(kWG), 0, st, e, count, par); break;
+    case 1: hipLaunchKernelGGL((k_gemv_b_grp<XT, MX>), dim3(wgs), dim3(kWG), 0, st, e, count, par); break;
+    case 2: hipLaunchKernelGGL(k_block_grp, dim3(wgs), dim3(kWG), 0, st, e, count, par); break;
+    default: hipLaunchKernelGGL(k_band_grp, dim3(count), dim3(kWG), 0, st, e, par); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_grouped(int dtype, bool mixed, const GroupEntry* e, int count, int wgs, int par, int which,
+                          hipStream_t st) {
+  switch (dtype) {
+    case 0: return mixed ? launch_grouped_t<double, true>(e, count, wgs, par, which, st)
+                         : launch_grouped_t<double, false>(e, count, wgs, par, which, st);
+    case 1: return mixed ? launch_grouped_t<float, true>(e, count, wgs, par, which, st)
+                         : launch_grouped_t<float, false>(e, count, wgs, par, which, st);
+    default: return mixed ? launch_grouped_t<uint16_t, true>(e, count, wgs, par, which, st)
+                          : launch_grouped_t<uint16_t, false>(e, count, wgs, par, which, st);
+  }
+}
+
+hipError_t launch_gather_states(const GroupEntry* e, int count, State* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_states, dim3((unsigned)((count + kWG - 1) / kWG)), dim3(kWG), 0, st, e, count, out);
+  return hipGetLastError();
+}
+
 template <typename XT, bool MX>
 static hipError_t launch_rotation_t(const Dims& D, const Bufs& B, int par, int which, hipStream_t st) {
   const State* sin = B.st + par;

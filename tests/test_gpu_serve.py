@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import flrgen
+import oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -159,8 +160,48 @@ def test_ragged_batch_equals_solo_solves(flr, ctx):
         assert r.mm_iters == s1.mm_iters and r.cg_iters == s1.cg_iters
         assert np.array_equal(bta, s1.beta)
         assert r.objective == s1.objective
+    # the same batch with exact inner solves against the oracle (Algorithm 2, FP64 bar)
+    o = flr.default_opts(inner_tol=1e-12)
+    betas = [np.zeros(i.p) for i in insts]
+    st, res = flr.flr_solve_batch(probs, l1, l2, 1e-7, opts=o, betas=betas)
+    for inst, a, b, r, bta in zip(insts, l1, l2, res, betas):
+        ref = oracle.solve(oracle.Problem.from_instance(inst), a, b, tol=1e-7, inner_tol=1e-12, method=oracle.ALG2)
+        err = np.max(np.abs(bta - ref.beta)) / np.max(np.abs(ref.beta))
+        print("  %-28s batch mm=%d | oracle mm=%d err=%.2e" % (inst.name, r.mm_iters, ref.mm_iters, err), flush=True)
+        assert r.status == flr.FLR_OK and r.mm_iters == ref.mm_iters
+        assert err <= 1e-8
+        assert abs(r.objective - ref.objective) <= 1e-11 * ref.objective
     with pytest.raises(flr.FlrError) as ei:  # the same handle twice
         flr.flr_solve_batch([probs[0], probs[0]], [0.1, 0.2], [0.1, 0.2], 1e-6)
     assert ei.value.status == flr.FLR_ERR_INVALID_ARG
     for p in probs:
         p.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_large_ragged_batch_in_grouped_launches(flr, ctx, precision):
+    # 18 problems over all three stored types, chain / lattice (banded M) / all pairs, p from 40 to 3000:
+    # one graph of grouped launches drives them all, and every result must equal its solo solve bit for bit
+    rng = np.random.default_rng(71)
+    insts, lam = [], []
+    specs = [("chain", 150, 3000), ("chain", 60, 300), ("lattice", 80, 400), ("allpairs", 30, 40), ("chain", 200, 1200),
+             ("lattice", 60, 144)]
+    for k in range(18):
+        graph, n, p = specs[k % len(specs)]
+        dtype = (flrgen.F64, flrgen.F32, flrgen.BF16)[k % 3]
+        inst = flrgen.small_instance(n, p, graph, dtype=dtype, seed=700 + k)
+        insts.append(inst)
+        lam.append((float(rng.uniform(0.05, 0.6)), float(rng.uniform(0.05, 0.8))))
+    prec = flr.FLR_PREC_FP64 if precision == "fp64" else flr.FLR_PREC_MIXED_FP32
+    o = flr.default_opts(precision=prec)
+    probs = [flr.Problem.from_instance(ctx, i) for i in insts]
+    solo = [p.solve(a, b, tol=1e-7, precision=prec) for p, (a, b) in zip(probs, lam)]
+    betas = [np.zeros(i.p) for i in insts]
+    st, res = flr.flr_solve_batch(probs, [a for a, _ in lam], [b for _, b in lam], 1e-7, opts=o, betas=betas)
+    for p in probs:
+        p.close()
+    print("  %s: MM %s" % (precision, [r.mm_iters for r in res]), flush=True)
+    for s1, r, bta in zip(solo, res, betas):
+        assert r.status == s1.status == flr.FLR_OK
+        assert (r.mm_iters, r.cg_iters, r.objective) == (s1.mm_iters, s1.cg_iters, s1.objective)
+        assert np.array_equal(bta, s1.beta)
