@@ -61,15 +61,82 @@ __device__ inline void band_assemble(const double* __restrict__ d, const int32_t
   __syncthreads();
 }
 
+// Blocked right-looking Cholesky of the assembled band for bands wider than
+// band_factor's LDS ring.  Panels of nb columns (nb = 16, fewer for very wide
+// bands so that a panel fits the band LDS) are loaded into LDS and factored
+// there, one pivot per step; the panel's columns of L are written out (Lb
+// scaled by 1/L_jj, LbT unscaled, rescaled by the caller), and the triangle
+// of the band that the panel reaches - columns j0 + nb .. j0 + nb + W - 2 -
+// is updated with one rank-nb pass in global memory (wave w takes every
+// fourth column, lanes its rows, coalesced), instead of one pass per pivot.
+// 256 threads; returns false in every thread on a pivot that is not
+// positive and finite.
+__device__ inline bool band_factor_blocked(double* __restrict__ Lb, double* __restrict__ LbT,
+                                           double* __restrict__ invd, int64_t p, int W, double* __restrict__ P) {
+  __shared__ double sh_inv[16];
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
+  const int nb = kBandLds / W < 16 ? kBandLds / W : 16;
+  for (int64_t j0 = 0; j0 < p; j0 += nb) {
+    const int w = (int)((p - j0) < (int64_t)nb ? (p - j0) : (int64_t)nb);
+    const double* src = Lb + j0 * W;  // the panel's columns are contiguous
+    for (int e = tid; e < w * W; e += nt) P[e] = src[e];
+    __syncthreads();
+    for (int jj = 0; jj < w; ++jj) {
+      const double piv = P[jj * W];
+      if (!(piv > 0.0) || !isfinite(piv)) return false;  // the same value in every thread
+      const double ljj = sqrt(piv), inv = 1.0 / ljj;
+      __syncthreads();  // every thread has the pivot before it is overwritten
+      for (int k = tid; k < W; k += nt) P[jj * W + k] = k ? P[jj * W + k] * inv : ljj;
+      if (tid == 0) sh_inv[jj] = inv;
+      __syncthreads();
+      // later panel columns: M(j' + k, j') -= L(j' + k, j) L(j', j), j' = j + d
+      const int rem = w - 1 - jj;
+      for (int e = tid; e < rem * W; e += nt) {
+        const int d = 1 + e / W, k = e - (d - 1) * W;
+        if (k < W - d) P[(jj + d) * W + k] = fma(-P[jj * W + k + d], P[jj * W + d], P[(jj + d) * W + k]);
+      }
+      __syncthreads();
+    }
+    for (int e = tid; e < w * W; e += nt) {
+      const int jj = e / W, k = e - jj * W;
+      const int64_t j = j0 + jj;
+      const double v = P[e];
+      if (k == 0) {
+        Lb[j * W] = v;
+        LbT[j * W] = v;
+        invd[j] = sh_inv[jj];
+      } else if (j + k < p) {
+        Lb[j * W + k] = v * sh_inv[jj];
+        LbT[(j + k) * W + k] = v;
+      }
+    }
+    // trailing triangle: column c = j0 + dcol, row c + di gets the sum over
+    // the panel columns whose band reaches both c and c + di
+    const int64_t cend = (j0 + w + W - 2) < p - 1 ? (j0 + w + W - 2) : p - 1;
+    for (int64_t c = j0 + w + wave; c <= cend; c += 4) {
+      const int dcol = (int)(c - j0);
+      int dimax = W - 1 < w + W - 2 - dcol ? W - 1 : w + W - 2 - dcol;
+      if ((int64_t)dimax > p - 1 - c) dimax = (int)(p - 1 - c);
+      for (int di = lane; di <= dimax; di += 64) {
+        const int jlo = dcol + di - (W - 1) > 0 ? dcol + di - (W - 1) : 0;
+        double sum = 0.0;
+        for (int jj = jlo; jj < w; ++jj) sum = fma(P[jj * W + dcol + di - jj], P[jj * W + dcol - jj], sum);
+        Lb[c * W + di] -= sum;
+      }
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
 // Right-looking Cholesky of the assembled band, in place.  Step j takes the
 // pivot, writes column j of L (to Lb and, transposed, to LbT) and subtracts
 // the outer product of its scaled column from columns j+1 .. j+bw.  Those
 // columns live in an LDS ring of W + 4 slots when it fits: column j + W + 3
 // enters at step j (into the slot column j - 1 left) from registers loaded
 // four steps earlier, so the global loads overlap four steps of updates.
-// Otherwise the columns are updated in Lb and column j is scaled one step
-// later.  256 threads; returns false in every thread when a pivot is not
-// positive and finite.
+// Wider bands take the blocked factorization above.  256 threads; returns
+// false in every thread when a pivot is not positive and finite.
 __device__ inline bool band_factor(double* __restrict__ Lb, double* __restrict__ LbT, double* __restrict__ invd,
                                    int64_t p, int W, double* __restrict__ lds) {
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -163,44 +230,7 @@ __device__ inline bool band_factor(double* __restrict__ Lb, double* __restrict__
       }
     }
   } else {
-    __syncthreads();
-    double inv_prev = 0.0, ljj_prev = 0.0;
-    int dmax_prev = -1;
-    for (int64_t j = 0; j < p; ++j) {
-      const int dmax = (int)((p - 1 - j) < (int64_t)(W - 1) ? (p - 1 - j) : (int64_t)(W - 1));
-      double* cj = Lb + j * W;
-      const double piv = cj[0];
-      if (!(piv > 0.0) || !isfinite(piv)) {
-        ok = false;
-        break;
-      }
-      const double ljj = sqrt(piv), inv = 1.0 / ljj;
-      double* colj = lds;  // scaled column j
-      for (int d = tid; d <= dmax; d += nt) {
-        const double v = d ? cj[d] * inv : ljj;
-        colj[d] = v;
-        LbT[(j + d) * W + d] = v;
-      }
-      if (tid == 0) invd[j] = inv;
-      if (j > 0)  // column j - 1 is final: scale it in place (by 1/L_jj twice, see above)
-        for (int d = tid; d <= dmax_prev; d += nt)
-          Lb[(j - 1) * W + d] = d ? Lb[(j - 1) * W + d] * (inv_prev * inv_prev) : ljj_prev;
-      __syncthreads();
-      for (int d1 = 1 + ty; d1 <= dmax; d1 += 16) {
-        const double s1 = colj[d1];
-        double* tgt = Lb + (j + d1) * W - d1;
-        for (int d2 = d1 + tx; d2 <= dmax; d2 += 16) tgt[d2] = fma(-s1, colj[d2], tgt[d2]);
-      }
-      inv_prev = inv;
-      ljj_prev = ljj;
-      dmax_prev = dmax;
-      __syncthreads();
-    }
-    if (ok && p > 0) {
-      for (int d = tid; d <= dmax_prev; d += nt)
-        Lb[(p - 1) * W + d] = d ? Lb[(p - 1) * W + d] * (inv_prev * inv_prev) : ljj_prev;
-      __syncthreads();
-    }
+    ok = band_factor_blocked(Lb, LbT, invd, p, W, lds);
   }
   // the rescale below reads invd (stored by thread 0) and LbT entries stored
   // by other threads: a full barrier orders those global stores (the ring
@@ -228,34 +258,37 @@ __device__ inline double readlane_f64(double v, int lane) {
 // already include 1/L_jj.  The dependent chain is one fma per step, on values
 // every lane holds: bu = b_j (final), and the next element's final value
 // b_{j+1} = pre - m b_j, where pre is b_{j+1} after the steps before j (read
-// from its lane one step early) and m its multiplier at step j (a broadcast
-// LDS read).  The ring update - one fma per register - and those reads stay
-// off that chain.  Elements j + 1, j + 2 live in register R0 or, in the last
-// two steps of a chunk, in the next ring register R1.
+// from its lane one step early) and m its multiplier at step j, which the
+// lane of element j+1 already holds among the step's ring multipliers (a
+// readlane, no LDS read on the chain).  The ring update - one fma per
+// register - and those reads stay off that chain; the ring multipliers of a
+// step are loaded DP steps ahead.  Elements j + 1, j + 2 live in register R0
+// or, in the last two steps of a chunk, in the next ring register R1.
 template <int NR, int SC, int R0>
 __device__ __forceinline__ void band_steps(double (&reg)[NR], double& bu, double& pre, const double* __restrict__ buf,
                                            int lc0, int lane) {
   constexpr int R1 = (R0 + 1) % NR;
-  double mc[NR], mn[NR];
+  constexpr int DP = SC < (NR <= 5 ? 4 : 2) ? SC : (NR <= 5 ? 4 : 2);  // steps of multipliers in flight
+  double mq[DP][NR];
 #pragma unroll
-  for (int r = 0; r < NR; ++r) mc[r] = buf[r * 64 + lane];
+  for (int d = 0; d < DP; ++d)
+#pragma unroll
+    for (int r = 0; r < NR; ++r) mq[d][r] = buf[(d * NR + r) * 64 + lane];
 #pragma unroll
   for (int l = 0; l < SC; ++l) {
     const int lc = lc0 + l;
     const int ln1 = (lc + 1) & 63, ln2 = (lc + 2) & 63;
-    const int r1 = lc + 1 < 64 ? R0 : R1;
-    if (l + 1 < SC) {
-#pragma unroll
-      for (int r = 0; r < NR; ++r) mn[r] = buf[((l + 1) * NR + r) * 64 + lane];
-    }
-    const double m1 = buf[(l * NR + r1) * 64 + ln1];  // broadcast
+    double(&mc)[NR] = mq[l % DP];
+    const double m1 = readlane_f64(lc + 1 < 64 ? mc[R0] : mc[R1], ln1);
 #pragma unroll
     for (int r = 0; r < NR; ++r) reg[r] = fma(-mc[r], bu, reg[r]);
     const double pre2 = readlane_f64(lc + 2 < 64 ? reg[R0] : reg[R1], ln2);
     bu = fma(-m1, bu, pre);
     pre = pre2;
+    if (l + DP < SC) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r) mc[r] = mn[r];
+      for (int r = 0; r < NR; ++r) mc[r] = buf[((l + DP) * NR + r) * 64 + lane];
+    }
   }
 }
 

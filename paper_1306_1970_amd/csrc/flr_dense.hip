@@ -238,46 +238,50 @@ __device__ inline double lane_value(double v, int l) {
 }
 
 // Triangular solves with the factor (one workgroup): forward L z = rhs, then
-// backward L^T out = z, both blocked by 64.  Per block the diagonal block is
-// staged in LDS with the reciprocals of its diagonal, and one wave
-// substitutes through it, the solved value passed between lanes by readlane.
-// Forward is right-looking: once block b is solved, all 256 threads subtract
-// its contribution from every later row (64 coalesced loads per row, all in
-// flight).  Backward is left-looking: each of 64 rows x 4 slices reads 16
-// consecutive entries of one column of L (a whole 128-byte line) per chunk.
+// backward L^T out = z, both blocked by 64 and right-looking.  Per block one
+// wave substitutes through the diagonal block (staged in LDS with the
+// reciprocals of its diagonal; the solved value passed between lanes by
+// readlane) while the other three waves stage the next diagonal block into
+// the second LDS buffer; then all 256 threads subtract the solved block from
+// every row still to come - forward, row i reads L[i][block] (64 coalesced
+// loads); backward, row j reads L[block][j], 64 consecutive entries of column
+// j - so each block costs one round of loads instead of one per earlier block.
 __global__ __launch_bounds__(kWG) void k_chol_solve(const double* __restrict__ Q, int64_t nd, int64_t p,
                                                     const double* __restrict__ rhs, double* __restrict__ z,
                                                     double* __restrict__ out) {
   constexpr int LD = kNB + 1;
-  __shared__ double Lb[kNB * LD];  // Lb[c * LD + r] = L[b*64 + r][b*64 + c]
-  __shared__ double rdg[kNB];      // 1 / L[b*64 + r][b*64 + r]
-  __shared__ double zb[kNB];       // the block just solved (forward)
-  __shared__ double part[4][kNB];
-  const int tid = threadIdx.x, r = tid & 63, sl = tid >> 6;
+  __shared__ double Lb[2][kNB * LD];  // Lb[.][c * LD + r] = L[b*64 + r][b*64 + c]
+  __shared__ double rdg[2][kNB];      // 1 / L[b*64 + r][b*64 + r]
+  __shared__ double zb[kNB];          // the block just solved
+  const int tid = threadIdx.x, r = tid & 63, wave = tid >> 6;
   const int nb = (int)(nd / kNB);
-  auto stage = [&](int b) {
+  // diagonal block b into buffer u by the threads first .. kWG - 1
+  auto stage = [&](int b, int u, int first) {
     const int64_t o = (int64_t)b * kNB;
-    for (int e = tid; e < kNB * kNB; e += kWG) {
+    for (int e = tid - first; e < kNB * kNB; e += kWG - first) {
       const int c = e >> 6, rr = e & 63;
-      Lb[c * LD + rr] = Q[(o + c) * nd + o + rr];
+      Lb[u][c * LD + rr] = Q[(o + c) * nd + o + rr];
     }
-    if (tid < kNB) rdg[tid] = 1.0 / Q[(o + tid) * nd + o + tid];
+    if (tid - first < kNB && tid >= first) rdg[u][tid - first] = 1.0 / Q[(o + tid - first) * nd + o + tid - first];
   };
   for (int64_t i = tid; i < nd; i += kWG) z[i] = i < p ? rhs[i] : 0.0;
+  stage(0, 0, 0);
+  __syncthreads();
   // forward: z holds the running right-hand side; block b is final once blocks < b are applied
   for (int b = 0; b < nb; ++b) {
-    stage(b);
-    __syncthreads();
-    if (sl == 0) {
+    const int u = b & 1;
+    if (wave == 0) {
       const int64_t i = (int64_t)b * kNB + r;
       double t = z[i];
       for (int c = 0; c < kNB; ++c) {
-        const double zc = lane_value(t, c) * rdg[c];
+        const double zc = lane_value(t, c) * rdg[u][c];
         if (r == c) t = zc;
-        else if (r > c) t = fma(-Lb[c * LD + r], zc, t);
+        else if (r > c) t = fma(-Lb[u][c * LD + r], zc, t);
       }
       z[i] = t;
       zb[r] = t;
+    } else if (b + 1 < nb) {
+      stage(b + 1, u ^ 1, 64);
     }
     __syncthreads();
     const double* Lc = Q + (int64_t)b * kNB * nd;  // column b*64 of L
@@ -289,26 +293,31 @@ __global__ __launch_bounds__(kWG) void k_chol_solve(const double* __restrict__ Q
     }
     __syncthreads();
   }
-  // backward: out_b = L_bb^-T (z_b - sum_{j > b} L_jb^T out_j)
+  // backward: z now holds the running right-hand side of L^T out = z
+  stage(nb - 1, (nb - 1) & 1, 0);
+  __syncthreads();
   for (int b = nb - 1; b >= 0; --b) {
-    const int64_t i = (int64_t)b * kNB + r;  // column of L
-    double s = 0.0;
-    for (int64_t j0 = (int64_t)(b + 1) * kNB + 16 * sl; j0 < nd; j0 += kNB) {
-      const double* qc = Q + i * nd + j0;
-#pragma unroll
-      for (int u = 0; u < 16; ++u) s = fma(qc[u], out[j0 + u], s);
-    }
-    part[sl][r] = s;
-    stage(b);
-    __syncthreads();
-    if (sl == 0) {
-      double t = z[i] - ((part[0][r] + part[1][r]) + (part[2][r] + part[3][r]));
+    const int u = b & 1;
+    if (wave == 0) {
+      const int64_t i = (int64_t)b * kNB + r;  // column of L
+      double t = z[i];
       for (int c = kNB - 1; c >= 0; --c) {
-        const double xc = lane_value(t, c) * rdg[c];
+        const double xc = lane_value(t, c) * rdg[u][c];
         if (r == c) t = xc;
-        else if (r < c) t = fma(-Lb[r * LD + c], xc, t);
+        else if (r < c) t = fma(-Lb[u][r * LD + c], xc, t);
       }
       out[i] = t;
+      zb[r] = t;
+    } else if (b > 0) {
+      stage(b - 1, u ^ 1, 64);
+    }
+    __syncthreads();
+    for (int64_t j = tid; j < (int64_t)b * kNB; j += kWG) {
+      const double* qc = Q + j * nd + (int64_t)b * kNB;  // L[b*64 .. b*64+63][j]
+      double s = 0.0;
+#pragma unroll 16
+      for (int c = 0; c < kNB; ++c) s = fma(qc[c], zb[c], s);
+      z[j] -= s;
     }
     __syncthreads();
   }

@@ -122,6 +122,26 @@ def test_lattice_q100_grid(flr, ctx):
                "col %d" % b)
 
 
+def test_lattice_wider_than_the_band_ring(flr, ctx):
+    # a 120 x 120 lattice: bandwidth 121 is wider than the band factor's LDS ring, so M is factored by the
+    # blocked path (panels of 16 pivots in LDS, rank-16 updates in global memory), single solve and grid
+    inst = flrgen.small_instance(60, 14400, "lattice", dtype=flrgen.F32, seed=41, lam1=0.3, lam2=0.5)
+    print("case %s W=121" % inst.name, flush=True)
+    prob = flr.Problem.from_instance(ctx, inst)
+    sol = prob.solve(0.3, 0.5, tol=1e-8, inner_tol=INNER, max_iter=6)
+    l1 = np.array([0.3, 0.1, 1.0, 0.5])
+    l2 = np.array([0.5, 0.2, 0.3, 2.0])
+    st, beta, res = prob.solve_grid(l1, l2, tol=1e-8, inner_tol=INNER, max_iter=4)
+    prob.close()
+    ref = _oracle(inst, 0.3, 0.5, ulp_samples=1, tol=1e-8, inner_tol=INNER, max_iter=6, method=oracle.ALG2)
+    _check(flr, sol, ref, inst, 0.3, 0.5, "single")
+    for b in range(l1.size):
+        ref = _oracle(inst, l1[b], l2[b], ulp_samples=0, tol=1e-8, inner_tol=INNER, max_iter=4, method=oracle.ALG2)
+        r = res[b]
+        _check(flr, _Sol(beta[b], r["status"], r["objective"], r["mm_iters"], r["cg_iters"]), ref, inst, l1[b], l2[b],
+               "col %d" % b)
+
+
 @pytest.mark.parametrize("dtype,n,p", [(flrgen.F64, 300, 7000), (flrgen.BF16, 120, 26000)])
 def test_wide_panels_fp64(flr, ctx, dtype, n, p):
     # one row panel per column panel of X^T u (all n rows, > 256 for f64) and more than 12 partial
