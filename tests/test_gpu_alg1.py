@@ -121,3 +121,37 @@ def test_profile_dense(flr, ctx):
     assert again.mm_iters == 1
     assert again.objective <= sol.objective
     assert sol.objective - again.objective <= 1e-8 * sol.objective
+
+
+def test_alg1_through_server_and_path(flr, ctx):
+    # an all-pairs problem (the graph Algorithm 1 is meant for): one request through the serving loop with
+    # method = Algorithm 1, then a three-point warm-started path, each against the oracle's Algorithm 1
+    inst = flrgen.small_instance(50, 60, "allpairs", dtype=flrgen.F64, seed=131)
+    prob = flr.Problem.from_instance(ctx, inst)
+    P = oracle.Problem.from_instance(inst)
+    srv = flr.flr_server_create(ctx.h, prob.footprint + (64 << 20), 2)
+    o = flr.default_opts(method=flr.FLR_METHOD_CHOLESKY)
+    t = flr.flr_server_submit(srv, prob.h, 0.3, 0.05, 1e-8, o)
+    beta = np.zeros(inst.p)
+    st, res = flr.flr_server_poll(srv, t, True, beta)
+    flr.flr_server_destroy(srv)
+    ref = oracle.solve(P, 0.3, 0.05, tol=1e-8, method=oracle.ALG1)
+
+    class _S:
+        pass
+
+    s = _S()
+    s.beta, s.status, s.objective, s.mm_iters, s.cg_iters = beta, st, res.objective, res.mm_iters, res.cg_iters
+    _check(flr, s, ref, "server allpairs")
+    l1 = np.array([0.5, 0.3, 0.1])
+    l2 = np.array([0.02, 0.05, 0.1])
+    st, betas, results = prob.solve_path(l1, l2, tol=1e-8, method=flr.FLR_METHOD_CHOLESKY)
+    prob.close()
+    b0 = None
+    for k in range(l1.size):
+        ref = oracle.solve(P, l1[k], l2[k], tol=1e-8, method=oracle.ALG1, beta0=b0)
+        s = _S()
+        r = results[k]
+        s.beta, s.status, s.objective, s.mm_iters, s.cg_iters = betas[k], r["status"], r["objective"], r["mm_iters"], r["cg_iters"]
+        _check(flr, s, ref, "path point %d" % k)
+        b0 = ref.beta

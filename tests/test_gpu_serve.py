@@ -205,3 +205,25 @@ def test_large_ragged_batch_in_grouped_launches(flr, ctx, precision):
         assert r.status == s1.status == flr.FLR_OK
         assert (r.mm_iters, r.cg_iters, r.objective) == (s1.mm_iters, s1.cg_iters, s1.objective)
         assert np.array_equal(bta, s1.beta)
+
+
+def test_grouped_batch_with_signal_approximation(flr, ctx):
+    # X = I problems (no X stored; the grouped A launch only forms the direction) in one f64 group with an
+    # explicit-X problem, chain and lattice graphs: every result equals its solo solve bit for bit
+    rng = np.random.default_rng(17)
+    y1 = rng.standard_normal(300)
+    y2 = rng.standard_normal(400)
+    dense = flrgen.small_instance(60, 500, "chain", dtype=flrgen.F64, seed=171)
+    probs = [flr.Problem.flsa(ctx, y1, flrgen.chain_edges(300)), flr.Problem.flsa(ctx, y2, flrgen.lattice_edges(20)),
+             flr.Problem.from_instance(ctx, dense)]
+    lam = [(0.2, 0.5), (0.1, 0.3), (0.3, 0.6)]
+    solo = [p.solve(a, b, tol=1e-8) for p, (a, b) in zip(probs, lam)]
+    betas = [np.zeros(p.p) for p in probs]
+    st, res = flr.flr_solve_batch(probs, [a for a, _ in lam], [b for _, b in lam], 1e-8, betas=betas)
+    for p in probs:
+        p.close()
+    print("  MM %s" % [r.mm_iters for r in res], flush=True)
+    for s1, r, bta in zip(solo, res, betas):
+        assert r.status == s1.status == flr.FLR_OK
+        assert (r.mm_iters, r.cg_iters, r.objective) == (s1.mm_iters, s1.cg_iters, s1.objective)
+        assert np.array_equal(bta, s1.beta)
