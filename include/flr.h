@@ -59,7 +59,15 @@ typedef enum {
 typedef enum { FLR_F64 = 0, FLR_F32 = 1, FLR_BF16 = 2 } flr_dtype;
 
 /* Arithmetic of the inner products with X (the p-scale terms, dot products,
- * objective and stopping tests are always FP64). */
+ * objective and stopping tests are always FP64).
+ *   FP64        X widened exactly from its stored type, FP64 accumulation.
+ *   MIXED_FP32  the PCG steps' products with X in FP32 (X read in its stored
+ *               type, f32 or bf16 widened to f32), with the FP64 residual
+ *               c - Q beta refreshed and the inner solve repeated until the
+ *               true FP64 residual meets the inner tolerance.
+ * There is no separate bf16-arithmetic mode: a bf16-stored X already halves
+ * the bytes each pass streams, and the products are bound by those bytes,
+ * so bf16 arithmetic would only lose accuracy. */
 typedef enum { FLR_PREC_FP64 = 0, FLR_PREC_MIXED_FP32 = 1 } flr_precision;
 
 /* Preconditioner of the PCG inner solve (Algorithm 2 uses M = lambda1 A +
