@@ -81,7 +81,10 @@ __global__ __launch_bounds__(kWG) void k_dense_assemble(int64_t p, int64_t nd, c
 // workgroup writes its own row blocks of L back into Q.  Q column-major, ld
 // nd; nrb = row blocks in the panel, the diagonal one included; *bad set on a
 // pivot that is not positive and finite.
-constexpr int kPR = 3;  // panel row blocks per workgroup besides the diagonal block
+// Panel row blocks per workgroup besides the diagonal block.  One is the
+// fastest measured (order 512: factorization 275 us against 310 us with two
+// and 345 us with three): fewer registers per lane, more workgroups per panel.
+constexpr int kPR = 1;
 
 __global__ __launch_bounds__(kWG) void k_chol_panel(double* __restrict__ Q, int64_t nd, int64_t kb, int nrb,
                                                     int* bad, double* __restrict__ diag) {
