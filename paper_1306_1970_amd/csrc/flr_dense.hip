@@ -429,14 +429,28 @@ static flr_status dfail(flr_status st, const std::string& m) {
 #define DCK(expr)                                                                                           \
   do {                                                                                                      \
     hipError_t e_ = (expr);                                                                                 \
-    if (e_ != hipSuccess)                                                                                   \
+    if (e_ != hipSuccess) {                                                                                 \
+      (void)hipGetLastError(); /* a failed call also leaves its error for the next check */                 \
       return dfail(e_ == hipErrorOutOfMemory ? FLR_ERR_OUT_OF_MEMORY : FLR_ERR_DEVICE,                      \
                    std::string(#expr) + ": " + hipGetErrorString(e_));                                      \
+    }                                                                                                       \
   } while (0)
 
-// Workspace and X^T X, on the first Algorithm 1 solve of a handle.
+// Workspace and X^T X, on the first Algorithm 1 solve of a handle; on any
+// failure the partial workspace is released, so a later call starts over.
+static flr_status dense_prepare_once(flr_problem h);
+
 static flr_status dense_prepare(flr_problem h) {
   if (h->dense) return FLR_OK;
+  const flr_status st = dense_prepare_once(h);
+  if (st != FLR_OK) {
+    (void)hipStreamSynchronize(h->stream);
+    dense_free(h);
+  }
+  return st;
+}
+
+static flr_status dense_prepare_once(flr_problem h) {
   const Dims& D = h->D;
   DenseWork* dw = new DenseWork;
   h->dense = dw;

@@ -40,9 +40,11 @@ static flr_status fail(flr_status st, const std::string& msg) {
 #define HIP_OR_FAIL(expr)                                                                                   \
   do {                                                                                                      \
     hipError_t e_ = (expr);                                                                                 \
-    if (e_ != hipSuccess)                                                                                   \
+    if (e_ != hipSuccess) {                                                                                 \
+      (void)hipGetLastError(); /* a failed call also leaves its error for the next check */                 \
       return fail(e_ == hipErrorOutOfMemory ? FLR_ERR_OUT_OF_MEMORY : FLR_ERR_DEVICE,                       \
                   std::string(#expr) + ": " + hipGetErrorString(e_));                                       \
+    }                                                                                                       \
   } while (0)
 
 namespace {
@@ -562,9 +564,11 @@ static flr_status create_impl(flr_ctx ctx, const void* X, flr_dtype x_dtype, int
 #define CK(expr)                                                                                           \
   do {                                                                                                     \
     hipError_t e_ = (expr);                                                                                \
-    if (e_ != hipSuccess)                                                                                  \
+    if (e_ != hipSuccess) {                                                                                \
+      (void)hipGetLastError(); /* a failed call also leaves its error for the next check */                \
       return bail(fail(e_ == hipErrorOutOfMemory ? FLR_ERR_OUT_OF_MEMORY : FLR_ERR_DEVICE,                 \
                        std::string(#expr) + ": " + hipGetErrorString(e_)));                                \
+    }                                                                                                      \
   } while (0)
   CK(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
   CK(hipEventCreateWithFlags(&h->ev[0], hipEventDisableTiming));

@@ -615,16 +615,31 @@ static flr_status gfail(flr_status st, const std::string& m) {
 #define GCK(expr)                                                                                           \
   do {                                                                                                      \
     hipError_t e_ = (expr);                                                                                 \
-    if (e_ != hipSuccess)                                                                                   \
+    if (e_ != hipSuccess) {                                                                                 \
+      (void)hipGetLastError(); /* a failed call also leaves its error for the next check */                 \
       return gfail(e_ == hipErrorOutOfMemory ? FLR_ERR_OUT_OF_MEMORY : FLR_ERR_DEVICE,                      \
                    std::string(#expr) + ": " + hipGetErrorString(e_));                                      \
+    }                                                                                                       \
   } while (0)
 
 // Workspace of the allocating entry point: kept on the handle while it holds
 // at least B columns (and a banded factor when one is needed), else replaced.
+// On any failure the partial workspace is released, so that a later call
+// does not take it for a usable one.
+static flr_status grid_prepare_once(flr_problem h, int B, bool band);
+
 static flr_status grid_prepare(flr_problem h, int B, bool band) {
   if (h->grid && h->grid->cap >= B && (h->grid->band || !band)) return FLR_OK;
   grid_free(h);
+  const flr_status st = grid_prepare_once(h, B, band);
+  if (st != FLR_OK) {
+    (void)hipStreamSynchronize(h->stream);
+    grid_free(h);
+  }
+  return st;
+}
+
+static flr_status grid_prepare_once(flr_problem h, int B, bool band) {
   GridWork* gw = new GridWork;
   h->grid = gw;
   gw->cap = B;

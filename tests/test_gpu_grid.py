@@ -246,3 +246,23 @@ def test_grid_workspace_is_charged_to_footprint(flr, ctx):
     W = inst.meta["q"] + 1
     assert after - before >= 4 * (2 * inst.p * W + 8 * inst.p) * 8
     prob.close()
+
+
+def test_grid_workspace_failure_leaves_the_handle_usable(flr, ctx):
+    # A 509 x 509 lattice (bandwidth 510) with 256 columns asks for about 541 GB of per-column band
+    # factors: the single workspace allocation fails with FLR_ERR_OUT_OF_MEMORY before any kernel runs.
+    # The partial workspace must be released, so a small grid on the same handle then works.
+    q = 509
+    inst = flrgen.small_instance(2, q * q, "lattice", dtype=flrgen.F32, seed=38, q=q)
+    prob = flr.Problem.from_instance(ctx, inst)
+    fp0 = prob.footprint
+    l1 = np.full(256, 0.5)
+    l2 = np.full(256, 0.5)
+    with pytest.raises(flr.FlrError) as ei:
+        prob.solve_grid(l1, l2, tol=1e-4, max_iter=1, max_cg=2)
+    assert ei.value.status == flr.FLR_ERR_OUT_OF_MEMORY
+    assert prob.footprint == fp0
+    st, beta, res = prob.solve_grid(l1[:2], l2[:2], tol=1e-4, max_iter=1, max_cg=2)
+    prob.close()
+    assert all(r["status"] in (flr.FLR_OK, flr.FLR_ERR_MAX_ITER) for r in res)
+    assert np.all(np.isfinite(beta))
