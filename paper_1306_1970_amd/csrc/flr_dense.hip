@@ -13,13 +13,15 @@
 //             the trailing lower triangle, tile by tile
 //   solve     L z = c, then L^T b = z, blocked by 64 in one workgroup
 //   objective f(b) in FP64: 1/2 ||y - X b||^2 (one pass over X) + penalties
-// The host drives the MM loop (one synchronization per MM iteration, which
-// costs little next to a factorization).
+// The host drives the MM loop: one MM step's launches are captured once per
+// solve as a HIP graph and replayed every iteration, with one
+// synchronization per iteration for f and the pivot flag.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -349,6 +351,11 @@ __global__ __launch_bounds__(kWG) void k_dense_rowres(const XT* __restrict__ X, 
   }
 }
 
+// The pivot flag cleared by a kernel (graphs here record no memset nodes).
+__global__ __launch_bounds__(kWG) void k_clear_flag(int* __restrict__ flag) {
+  if (threadIdx.x == 0) *flag = 0;
+}
+
 // G[j][j] = 1 for j < p (the Gram matrix of X = I; the rest stays zero).
 __global__ __launch_bounds__(kWG) void k_unit_diagonal(double* __restrict__ G, int64_t nd, int64_t p) {
   const int64_t j = (int64_t)blockIdx.x * kWG + threadIdx.x;
@@ -395,6 +402,12 @@ void set_last_error(const std::string& s);
 hipError_t launch_init(const Dims& D, const Bufs& B, const double* warm, int use_warm, hipStream_t st);
 bool is_device_pointer(const void* p);
 
+struct DenseOut {
+  double f;
+  int bad;
+  int pad;
+};
+
 struct DenseWork {
   int64_t nd = 0;
   double* G = nullptr;    // X^T X, nd x nd column-major (padding zero)
@@ -407,6 +420,7 @@ struct DenseWork {
   double* scal = nullptr; // f
   double* diag = nullptr; // factored diagonal block in flight (64 x 64)
   int* bad = nullptr;
+  DenseOut* h_out = nullptr;  // pinned: f of the candidate and the pivot flag of the last step
   size_t bytes = 0;
 };
 
@@ -416,6 +430,7 @@ void dense_free(flr_problem h) {
   for (void* p : {(void*)dw->G, (void*)dw->Q, (void*)dw->a, (void*)dw->w, (void*)dw->z, (void*)dw->xn, (void*)dw->rr,
                   (void*)dw->scal, (void*)dw->diag, (void*)dw->bad})
     if (p) (void)hipFree(p);
+  if (dw->h_out) (void)hipHostFree(dw->h_out);
   h->footprint -= dw->bytes;
   delete dw;
   h->dense = nullptr;
@@ -476,6 +491,7 @@ static flr_status dense_prepare_once(flr_problem h) {
   DCK(al(&dw->scal, 4, sizeof(double)));
   DCK(al(&dw->diag, (size_t)kNB * kNB, sizeof(double)));
   DCK(al(&dw->bad, 1, sizeof(int)));
+  DCK(hipHostMalloc(reinterpret_cast<void**>(&dw->h_out), sizeof(DenseOut), hipHostMallocDefault));
   if (D.flsa) {  // X = I: X^T X = I on the leading p x p block (G was zeroed on this stream)
     hipLaunchKernelGGL(k_unit_diagonal, dim3((unsigned)((D.p + kWG - 1) / kWG)), dim3(kWG), 0, h->stream, dw->G,
                        dw->nd, D.p);
@@ -546,6 +562,30 @@ static hipError_t dense_factor(flr_problem h) {
   return hipSuccess;
 }
 
+// One MM step of Algorithm 1 enqueued on the problem's stream: reweighting
+// at the iterate, assembly of Q, its factorization and the two triangular
+// solves into the candidate xn, the candidate's objective, and copies of that
+// objective and of the pivot flag into pinned host memory.
+static hipError_t dense_step(flr_problem h, double l1, double l2, double eps) {
+  const Dims& D = h->D;
+  DenseWork* dw = h->dense;
+  const unsigned pb = (unsigned)((D.p + kWG - 1) / kWG);
+  hipLaunchKernelGGL(k_dense_reweight, dim3(pb), dim3(kWG), 0, h->stream, D.p, h->B.x, h->B.rowptr, h->B.col, eps,
+                     dw->a, dw->w);
+  hipLaunchKernelGGL(k_dense_assemble, dim3((unsigned)dw->nd), dim3(kWG), 0, h->stream, D.p, dw->nd, dw->G, dw->Q,
+                     dw->a, dw->w, h->B.rowptr, h->B.col, l1, l2);
+  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(kWG), 0, h->stream, dw->bad);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = dense_factor(h)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(kWG), 0, h->stream, dw->Q, dw->nd, D.p, h->B.c, dw->z, dw->xn);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = dense_objective(h, dw->xn, l1, l2)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(&dw->h_out->f, dw->scal, sizeof(double), hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
+    return e;
+  return hipMemcpyAsync(&dw->h_out->bad, dw->bad, sizeof(int), hipMemcpyDeviceToHost, h->stream);
+}
+
 // One solve by Algorithm 1: the MM loop with an exact (Cholesky) solve per
 // iteration.  Same outer test, initialization, warm starts and outputs as the
 // PCG path (cg_iters = 0, rel_residual = 0).
@@ -585,30 +625,42 @@ flr_status dense_run(flr_problem h, double l1, double l2, double tol, const flr_
   int status = FLR_ERR_MAX_ITER;
   double re = 0.0, f_new = f_old;
   int32_t it = 0;
-  const unsigned pb = (unsigned)((D.p + kWG - 1) / kWG);
+  // One MM step's device work is captured once per solve as a HIP graph and
+  // replayed every iteration (FLR_DENSE_GRAPH=0: launched eagerly instead);
+  // the candidate is accepted into the iterate outside the graph, since a
+  // failed pivot must leave the iterate as it was.
+  const char* gv = std::getenv("FLR_DENSE_GRAPH");
+  const bool use_graph = !(gv && gv[0] == '0');
+  struct GraphGuard {
+    hipGraphExec_t exec = nullptr;
+    ~GraphGuard() {
+      if (exec) (void)hipGraphExecDestroy(exec);
+    }
+  } gg;
+  if (use_graph) {
+    DCK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    const hipError_t body = dense_step(h, l1, l2, eps);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(h->stream, &graph);
+    if (body != hipSuccess && graph) (void)hipGraphDestroy(graph);
+    DCK(body);
+    DCK(ec);
+    const hipError_t ei = hipGraphInstantiate(&gg.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    DCK(ei);
+  }
   while (it < max_iter) {
-    hipLaunchKernelGGL(k_dense_reweight, dim3(pb), dim3(kWG), 0, h->stream, D.p, x, h->B.rowptr, h->B.col, eps,
-                       dw->a, dw->w);
-    hipLaunchKernelGGL(k_dense_assemble, dim3((unsigned)dw->nd), dim3(kWG), 0, h->stream, D.p, dw->nd, dw->G, dw->Q,
-                       dw->a, dw->w, h->B.rowptr, h->B.col, l1, l2);
-    DCK(hipGetLastError());
-    DCK(hipMemsetAsync(dw->bad, 0, sizeof(int), h->stream));
-    DCK(dense_factor(h));
-    hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(kWG), 0, h->stream, dw->Q, dw->nd, D.p, h->B.c, dw->z, dw->xn);
-    DCK(hipGetLastError());
-    // the objective of the candidate and the pivot flag come back in one synchronization
-    DCK(dense_objective(h, dw->xn, l1, l2));
-    int bad = 0;
-    double f_c = 0.0;
-    DCK(hipMemcpyAsync(&bad, dw->bad, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-    DCK(hipMemcpyAsync(&f_c, dw->scal, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    if (gg.exec)
+      DCK(hipGraphLaunch(gg.exec, h->stream));
+    else
+      DCK(dense_step(h, l1, l2, eps));
     DCK(hipStreamSynchronize(h->stream));
-    if (bad) {
+    if (dw->h_out->bad) {
       status = FLR_ERR_NUMERICAL;
       break;
     }
     DCK(hipMemcpyAsync(x, dw->xn, (size_t)D.p * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
-    f_new = f_c;
+    f_new = dw->h_out->f;
     ++it;
     re = f_old != 0.0 ? std::fabs(f_new - f_old) / std::fabs(f_old) : std::fabs(f_new - f_old);
     f_old = f_new;

@@ -155,3 +155,21 @@ def test_alg1_through_server_and_path(flr, ctx):
         s.beta, s.status, s.objective, s.mm_iters, s.cg_iters = betas[k], r["status"], r["objective"], r["mm_iters"], r["cg_iters"]
         _check(flr, s, ref, "path point %d" % k)
         b0 = ref.beta
+
+
+def test_alg1_graph_replay_matches_eager(flr, ctx, monkeypatch):
+    # every MM step of Algorithm 1 replays one captured graph; the eager launches (FLR_DENSE_GRAPH=0) must
+    # give the same bits, and so must a second graph solve after the eager one on the same handle
+    inst = flrgen.small_instance(90, 330, "allpairs", dtype=flrgen.F32, seed=141, lam1=0.3, lam2=0.02)
+    prob = flr.Problem.from_instance(ctx, inst)
+    g1 = prob.solve(0.3, 0.02, tol=1e-9, method=flr.FLR_METHOD_CHOLESKY)
+    monkeypatch.setenv("FLR_DENSE_GRAPH", "0")
+    e1 = prob.solve(0.3, 0.02, tol=1e-9, method=flr.FLR_METHOD_CHOLESKY)
+    monkeypatch.delenv("FLR_DENSE_GRAPH")
+    g2 = prob.solve(0.3, 0.02, tol=1e-9, method=flr.FLR_METHOD_CHOLESKY)
+    prob.close()
+    print("  graph mm=%d, eager mm=%d" % (g1.mm_iters, e1.mm_iters), flush=True)
+    assert g1.mm_iters > 10
+    for s in (g1, g2):
+        assert (s.status, s.mm_iters, s.objective) == (e1.status, e1.mm_iters, e1.objective)
+        assert np.array_equal(s.beta, e1.beta)
