@@ -631,12 +631,15 @@ flr_status dense_run(flr_problem h, double l1, double l2, double tol, const flr_
   // failed pivot must leave the iterate as it was.
   const char* gv = std::getenv("FLR_DENSE_GRAPH");
   const bool use_graph = !(gv && gv[0] == '0');
-  struct GraphGuard {
+  struct GraphGuard {  // on every return: a replay still in flight finishes before its graph goes
+    hipStream_t st;
     hipGraphExec_t exec = nullptr;
     ~GraphGuard() {
-      if (exec) (void)hipGraphExecDestroy(exec);
+      if (!exec) return;
+      (void)hipStreamSynchronize(st);
+      (void)hipGraphExecDestroy(exec);
     }
-  } gg;
+  } gg{h->stream};
   if (use_graph) {
     DCK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
     const hipError_t body = dense_step(h, l1, l2, eps);

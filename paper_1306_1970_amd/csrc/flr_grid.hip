@@ -772,10 +772,14 @@ static flr_status grid_run(flr_problem h, GridWork* gw, GridHost hb, const doubl
     for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
     graphs.clear();
   };
-  struct GraphGuard {
+  struct GraphGuard {  // on every return: replays still in flight finish before their graphs go
+    hipStream_t st;
     std::function<void()> f;
-    ~GraphGuard() { f(); }
-  } guard{drop_graphs};
+    ~GraphGuard() {
+      (void)hipStreamSynchronize(st);
+      f();
+    }
+  } guard{h->stream, drop_graphs};
   auto run_period = [&](int64_t st) -> hipError_t {
     unsigned mask = 0;
     for (int k = 0; k < check_every; ++k)
