@@ -30,6 +30,7 @@ namespace flr {
 
 constexpr int kBandLds = 13312;   // doubles of LDS the band routines use (104 KiB)
 constexpr int kBandMaxW = 1025;   // widest band the sweeps handle (NR = 17 ring registers)
+constexpr int kPanelMaxW = 107;   // widest band the register-panel factorization takes (its LDS window)
 
 // Ring registers per lane: 64*NR slots must hold the bw elements ahead of the
 // current one plus the 64 of the chunk being consumed.
@@ -61,8 +62,14 @@ __device__ inline void band_assemble(const double* __restrict__ d, const int32_t
   __syncthreads();
 }
 
-// Blocked right-looking Cholesky of the assembled band for bands wider than
-// band_factor's LDS ring.  Panels of nb columns (nb = 16, fewer for very wide
+__device__ inline double readlane_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Blocked right-looking Cholesky of the assembled band for bands too wide for
+// the register-panel factorization's LDS window (below).  Panels of nb columns (nb = 16, fewer for very wide
 // bands so that a panel fits the band LDS) are loaded into LDS and factored
 // there, one pivot per step; the panel's columns of L are written out (Lb
 // scaled by 1/L_jj, LbT unscaled, rescaled by the caller), and the triangle
@@ -129,128 +136,208 @@ __device__ inline bool band_factor_blocked(double* __restrict__ Lb, double* __re
   return true;
 }
 
-// Right-looking Cholesky of the assembled band, in place.  Step j takes the
-// pivot, writes column j of L (to Lb and, transposed, to LbT) and subtracts
-// the outer product of its scaled column from columns j+1 .. j+bw.  Those
-// columns live in an LDS ring of W + 4 slots when it fits: column j + W + 3
-// enters at step j (into the slot column j - 1 left) from registers loaded
-// four steps earlier, so the global loads overlap four steps of updates.
-// Wider bands take the blocked factorization above.  256 threads; returns
-// false in every thread when a pivot is not positive and finite.
-__device__ inline bool band_factor(double* __restrict__ Lb, double* __restrict__ LbT, double* __restrict__ invd,
-                                   int64_t p, int W, double* __restrict__ lds) {
-  const int tid = threadIdx.x, nt = blockDim.x;
+// Right-looking Cholesky of the assembled band in panels of NB columns, for
+// bands narrow enough that the active window fits in LDS.  The window -
+// columns j0 .. j0 + NB + W - 2 while the panel that starts at column j0 is
+// factored - is a ring of R = NB + W - 1 columns of W entries (column c in
+// slot c mod R).  Per panel:
+//  * wave 0 takes the panel's columns into registers (lane l holds rows
+//    j0 + l and j0 + 64 + l) and factors them there: each pivot and the
+//    multipliers of the later panel columns come from the lanes that hold
+//    them (readlane), so the panel needs no barrier.  It leaves the panel's
+//    rows of L in LDS (Lp) and nothing else, to keep this serial part short;
+//  * after one barrier waves 1-3 write the panel's columns of L to Lb, LbT
+//    and invd while wave 0 moves the next NB columns of the assembled band,
+//    loaded one panel earlier, into the panel's freed slots and issues the
+//    loads for the panel after (its memory counter then holds only those
+//    loads, so waiting for them never waits for the scattered stores); then
+//    the workgroup subtracts L21 L21^T (L21: the rows of Lp below the panel)
+//    from the trailing triangle (columns j0 + NB .. j0 + NB + W - 2):
+//    thread (tx, ty) keeps its entries (row offset tx + 16 c, column offset
+//    ty + 16 a) in registers over the panel's NB pivots.
+// Every entry receives the same fused multiply-adds in the same pivot order as
+// in a one-pivot-per-step right-looking factorization (an update from a pivot
+// whose band does not reach the entry multiplies by an exact zero), so the
+// factor is the same bit for bit; the trailing triangle makes one LDS round
+// trip per NB pivots instead of one per pivot, with two barriers per panel.
+// 256 threads; false in every thread on a pivot that is not positive and
+// finite.
+template <int NB>
+__device__ inline bool band_factor_panels(double* __restrict__ Lb, double* __restrict__ LbT,
+                                          double* __restrict__ invd, int64_t p, int W, double* __restrict__ lds) {
+  constexpr int LP = NB + 1;                   // Lp row stride, odd: 16 consecutive rows in distinct banks
+  constexpr int NXT = (NB * kPanelMaxW + 63) / 64;  // entering band entries per lane of wave 0
+  constexpr int kTB = 7;                       // 16-wide blocks of the trailing triangle (W - 1 <= 112)
+  __shared__ int sh_bad;
+  __shared__ double sh_inv[NB];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tx = tid & 15, ty = tid >> 4;
-  constexpr int E = 4;  // extra ring slots = load-ahead distance in steps
-  constexpr int kRingB = 7;  // 16-wide blocks of offsets 1 .. W - 1 in the ring (W <= 113)
-  const int R = W + E;
-  const bool ring = (int64_t)R * W <= kBandLds && W <= nt && W - 1 <= 16 * kRingB;
-  bool ok = true;
-  if (ring) {
-    const int64_t ncol = p < (int64_t)(W + E - 1) ? p : (int64_t)(W + E - 1);
-    for (int64_t i = tid; i < ncol * W; i += nt) lds[i] = Lb[i];
-    double nxt[E];  // entry tid of columns j + W + 3 (+ u) waiting to enter the ring
+  const int R = NB + W - 1;
+  double* Lp = lds + R * W;  // rows j0 .. j0 + R - 1 of the panel's columns of L, LP apart
+  const int64_t pw = p * (int64_t)W;
+  {
+    const int64_t n0 = (p < R ? p : (int64_t)R) * W;
+    for (int64_t i = tid; i < n0; i += 256) lds[i] = Lb[i];
+  }
+  double nxt[NXT];
 #pragma unroll
-    for (int u = 0; u < E; ++u) {
-      const int64_t c = (int64_t)W + E - 1 + u;
-      nxt[u] = (tid < W && c < p) ? Lb[c * W + tid] : 0.0;
-    }
-    __syncthreads();
-    int jr = 0;  // j mod R, kept incrementally (ring positions stay 32-bit)
-    for (int64_t jb = 0; jb < p && ok; jb += E) {
+  for (int q = 0; q < NXT; ++q) {
+    const int e = lane + 64 * q;
+    const int64_t g = (int64_t)R * W + e;
+    nxt[q] = (wave == 0 && e < NB * W && g < pw) ? Lb[g] : 0.0;
+  }
+  if (tid == 0) sh_bad = 0;
+  int s0 = 0;  // ring slot of column j0
+  for (int64_t j0 = 0; j0 < p; j0 += NB) {
+    const int w = (p - j0) < (int64_t)NB ? (int)(p - j0) : NB;
+    lds_barrier();
+    if (wave == 0) {
+      double x0[NB], x1[NB];
 #pragma unroll
-      for (int u = 0; u < E; ++u) {
-        const int64_t j = jb + u;
-        if (j >= p) break;
-        const int dmax = (int)((p - 1 - j) < (int64_t)(W - 1) ? (p - 1 - j) : (int64_t)(W - 1));
-        const double* cj = lds + jr * W;
-        // Every LDS read of the step is issued before the pivot's square root
-        // and reciprocal: the pivot, this thread's entry of column j (W <= nt,
-        // so one per thread), the column entries of its update pairs and the
-        // targets of those pairs.  Reads are unconditional at indices clamped
-        // into the column (a guarded load waits for itself); the rank-1 update
-        // of columns j+1 .. j+dmax gives thread (tx, ty) the pairs
-        // d1 = 1 + ty + 16 a (column), d2 = 1 + tx + 16 c (row), d1 <= d2, all
-        // distinct, so its targets are read before any is written.
-        const double piv = cj[0];
-        const double cown = cj[tid < W ? tid : W - 1];
-        double cr[kRingB], cc[kRingB], tv[kRingB][kRingB];
+      for (int jj = 0; jj < NB; ++jj) {
+        const int slot = s0 + jj < R ? s0 + jj : s0 + jj - R;
+        const int k0 = lane - jj, k1 = lane + 64 - jj;  // entries of column j0 + jj in the lane's rows
+        x0[jj] = (jj < w && k0 >= 0 && k0 < W) ? lds[slot * W + k0] : 0.0;
+        x1[jj] = (jj < w && k1 < W) ? lds[slot * W + k1] : 0.0;
+      }
+      bool bad = false;
 #pragma unroll
-        for (int a = 0; a < kRingB; ++a) {
-          const int d = 1 + 16 * a;
-          cr[a] = cj[d + tx < W ? d + tx : W - 1];
-          cc[a] = cj[d + ty < W ? d + ty : W - 1];
-        }
-#pragma unroll
-        for (int a = 0; a < kRingB; ++a) {
-          const int d1 = 1 + ty + 16 * a;
-          const int slot = jr + d1 < R ? jr + d1 : jr + d1 - R;
-          const double* tgt = lds + slot * W - d1;
-#pragma unroll
-          for (int c = a; c < kRingB; ++c) {
-            const int d2 = 1 + tx + 16 * c;
-            if (d1 <= d2 && d2 <= dmax) tv[a][c] = tgt[d2];
-          }
-        }
+      for (int jj = 0; jj < NB; ++jj) {
+        if (jj >= w) break;
+        const double piv = readlane_f64(x0[jj], jj);
         if (!(piv > 0.0) || !isfinite(piv)) {
-          ok = false;
+          bad = true;
           break;
         }
-        const double ljj = sqrt(piv), inv = 1.0 / ljj;
-        if (tid <= dmax) {
-          const double v = tid ? cown * inv : ljj;
-          Lb[j * W + tid] = tid ? v * inv : ljj;
-          LbT[(j + tid) * W + tid] = v;
-        }
-        if (tid == 0) invd[j] = inv;
-        double sr[kRingB], scl[kRingB];
+        const double ljj = sqrt(piv), rj = 1.0 / ljj;
+        if (lane == 0) sh_inv[jj] = rj;
+        const double l0 = lane > jj ? x0[jj] * rj : (lane == jj ? ljj : 0.0);
+        const double l1 = x1[jj] * rj;
+        x0[jj] = l0;
+        x1[jj] = l1;
 #pragma unroll
-        for (int a = 0; a < kRingB; ++a) {
-          const int d = 1 + 16 * a;
-          sr[a] = d + tx <= dmax ? cr[a] * inv : 0.0;
-          scl[a] = d + ty <= dmax ? cc[a] * inv : 0.0;
-        }
-#pragma unroll
-        for (int a = 0; a < kRingB; ++a) {
-          const int d1 = 1 + ty + 16 * a;
-          const int slot = jr + d1 < R ? jr + d1 : jr + d1 - R;
-          double* tgt = lds + slot * W - d1;
-#pragma unroll
-          for (int c = a; c < kRingB; ++c) {
-            const int d2 = 1 + tx + 16 * c;
-            if (d1 <= d2 && d2 <= dmax) tgt[d2] = fma(-scl[a], sr[c], tv[a][c]);
+        for (int c = jj + 1; c < NB; ++c) {
+          if (c < w) {
+            const double lc = readlane_f64(l0, c);
+            x0[c] = fma(-l0, lc, x0[c]);
+            x1[c] = fma(-l1, lc, x1[c]);
           }
         }
-        const int64_t cin = j + W + E - 1;  // enters the ring now (in slot (j - 1) mod R); first updated at step j + E
-        if (tid < W && cin < p) lds[(jr == 0 ? R - 1 : jr - 1) * W + tid] = nxt[u];
-        jr = jr + 1 == R ? 0 : jr + 1;
-        const int64_t cnx = cin + E;
-        nxt[u] = (tid < W && cnx < p) ? Lb[cnx * W + tid] : 0.0;
-        lds_barrier();  // the loads of nxt stay in flight for E steps
+      }
+      if (bad) {
+        if (lane == 0) sh_bad = 1;
+      } else {
+#pragma unroll
+        for (int jj = 0; jj < NB; ++jj) {
+          if (lane < R) Lp[lane * LP + jj] = x0[jj];
+          if (lane + 64 < R) Lp[(lane + 64) * LP + jj] = x1[jj];
+        }
       }
     }
-  } else {
-    ok = band_factor_blocked(Lb, LbT, invd, p, W, lds);
+    lds_barrier();
+    if (sh_bad) return false;
+    if (wave == 0) {
+      // the panel's slots take the columns entering the window, then the
+      // loads for the next panel go out
+#pragma unroll
+      for (int q = 0; q < NXT; ++q) {
+        const int e = lane + 64 * q;
+        if (e < NB * W && (j0 + R) * W + e < pw) {
+          const int ce = e / W;
+          const int slot = s0 + ce < R ? s0 + ce : s0 + ce - R;
+          lds[slot * W + (e - ce * W)] = nxt[q];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < NXT; ++q) {
+        const int e = lane + 64 * q;
+        const int64_t g = (j0 + NB + R) * W + e;
+        nxt[q] = (e < NB * W && g < pw) ? Lb[g] : 0.0;
+      }
+    } else {
+      // the panel's columns of L: Lb scaled by 1/L_jj below the diagonal,
+      // LbT unscaled (the caller scales its rows), invd
+      const int k = tid - 64;
+      for (int jj = 0; jj < w; ++jj) {
+        const int64_t j = j0 + jj;
+        if (k < W && j + k < p) {
+          const double v = Lp[(jj + k) * LP + jj];
+          Lb[j * W + k] = k ? v * sh_inv[jj] : v;
+          LbT[(j + k) * W + k] = v;
+        }
+      }
+      if (k < w) invd[j0 + k] = sh_inv[k];
+    }
+    if (j0 + NB < p) {
+      const int64_t rest = p - 1 - (j0 + NB);
+      const int cmax = rest < (int64_t)(W - 2) ? (int)rest : W - 2;
+      double t[kTB][kTB];
+#pragma unroll
+      for (int a = 0; a < kTB; ++a) {
+        const int u = ty + 16 * a, uc = u < W - 2 ? u : W - 2;
+        const int slot = s0 + NB + uc < R ? s0 + NB + uc : s0 + NB + uc - R;
+#pragma unroll
+        for (int c = a; c < kTB; ++c) {
+          const int v = tx + 16 * c;
+          t[a][c] = (u <= v && v <= cmax) ? lds[slot * W + (v - u)] : 0.0;
+        }
+      }
+#pragma unroll 2
+      for (int jj = 0; jj < NB; ++jj) {
+        double lu[kTB], lv[kTB];
+#pragma unroll
+        for (int a = 0; a < kTB; ++a) {
+          const int u = ty + 16 * a, v = tx + 16 * a;
+          lu[a] = Lp[(NB + (u < W - 2 ? u : W - 2)) * LP + jj];
+          lv[a] = Lp[(NB + (v < W - 2 ? v : W - 2)) * LP + jj];
+        }
+        // every tile entry is updated (entries outside the triangle hold
+        // values that are never stored), so no per-entry selects
+#pragma unroll
+        for (int a = 0; a < kTB; ++a)
+#pragma unroll
+          for (int c = a; c < kTB; ++c) t[a][c] = fma(-lu[a], lv[c], t[a][c]);
+      }
+#pragma unroll
+      for (int a = 0; a < kTB; ++a) {
+        const int u = ty + 16 * a, uc = u < W - 2 ? u : W - 2;
+        const int slot = s0 + NB + uc < R ? s0 + NB + uc : s0 + NB + uc - R;
+#pragma unroll
+        for (int c = a; c < kTB; ++c) {
+          const int v = tx + 16 * c;
+          if (u <= v && v <= cmax) lds[slot * W + (v - u)] = t[a][c];
+        }
+      }
+    }
+    s0 = s0 + NB < R ? s0 + NB : s0 + NB - R;
   }
-  // the rescale below reads invd (stored by thread 0) and LbT entries stored
-  // by other threads: a full barrier orders those global stores (the ring
-  // loop's last barrier orders LDS only)
+  return true;
+}
+
+// Cholesky factor of the assembled band, in place: the register-panel
+// factorization above when its window fits the band LDS (W <= 107), the
+// blocked one with the trailing update in global memory otherwise.  256
+// threads; returns false in every thread when a pivot is not positive and
+// finite.
+__device__ inline bool band_factor(double* __restrict__ Lb, double* __restrict__ LbT, double* __restrict__ invd,
+                                   int64_t p, int W, double* __restrict__ lds) {
+  constexpr int NB = 8;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const bool panels = W >= 2 && W <= kPanelMaxW && (int64_t)(NB + W - 1) * (W + NB + 1) <= kBandLds;
+  const bool ok = panels ? band_factor_panels<NB>(Lb, LbT, invd, p, W, lds)
+                         : band_factor_blocked(Lb, LbT, invd, p, W, lds);
+  // the rescale below reads invd (stored by lane 0) and LbT entries stored
+  // by other threads: a full barrier orders those global stores (the panel
+  // loop's barriers order LDS only)
   __syncthreads();
-  if (ok) {  // rows of L scaled by their own 1/L_ii (the backward sweep's multipliers)
-    const int64_t tot = p * (int64_t)W;
-    for (int64_t idx = tid; idx < tot; idx += nt) {
-      const int64_t i = idx / W;
-      if (idx - i * W) LbT[idx] *= invd[i];
+  if (ok) {  // rows of L scaled by their own 1/L_ii (the backward sweep's multipliers): a wave per row
+    for (int64_t i = tid >> 6; i < p; i += nt >> 6) {
+      const double s = invd[i];
+      for (int k = 1 + (tid & 63); k < W; k += 64) LbT[i * W + k] *= s;
     }
     __syncthreads();
   }
   return ok;
-}
-
-__device__ inline double readlane_f64(double v, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-  return __hiloint2double(hi, lo);
 }
 
 // SC steps of the sweep by wave 0: elements t0 .. t0 + SC - 1, held in

@@ -2,8 +2,8 @@
 
 The small parity cases of test_gpu_parity.py do not reach every branch that
 the benchmark configurations run: the headline chain at n = 1000, p = 10^4;
-the 100 x 100 lattice, whose banded factor (bandwidth 100) uses the widest
-LDS ring of the factorization; more than 12 row-panel partial sums per
+the 100 x 100 lattice, whose banded factor (bandwidth 100) uses every block
+of the register-panel factorization's trailing triangle; more than 12 row-panel partial sums per
 column panel and column panels of more than 256 rows in the X^T u kernel
 (the c4 shape); requests through the serving loop; zero columns of X and
 non-finite warm starts.  Where the oracle would need minutes for a whole
@@ -96,7 +96,7 @@ def _lattice100(seed=101, n=150):
 
 
 def test_lattice_q100_banded(flr, ctx):
-    # bandwidth 100: the band factor runs its LDS ring with every offset block (W = 101)
+    # bandwidth 100 (W = 101): the band factor runs in register panels with its window in LDS
     inst = _lattice100()
     print("case %s capped at 4 MM iterations" % inst.name, flush=True)
     prob = flr.Problem.from_instance(ctx, inst)
@@ -122,9 +122,10 @@ def test_lattice_q100_grid(flr, ctx):
                "col %d" % b)
 
 
-def test_lattice_wider_than_the_band_ring(flr, ctx):
-    # a 120 x 120 lattice: bandwidth 121 is wider than the band factor's LDS ring, so M is factored by the
-    # blocked path (panels of 16 pivots in LDS, rank-16 updates in global memory), single solve and grid
+def test_lattice_wider_than_the_band_window(flr, ctx):
+    # a 120 x 120 lattice: bandwidth 120 (W = 121) is wider than the register-panel factor's LDS window
+    # (W <= 107), so M is factored by the blocked path (panels of 16 pivots in LDS, rank-16 updates in
+    # global memory), single solve and grid
     inst = flrgen.small_instance(60, 14400, "lattice", dtype=flrgen.F32, seed=41, lam1=0.3, lam2=0.5)
     print("case %s W=121" % inst.name, flush=True)
     prob = flr.Problem.from_instance(ctx, inst)

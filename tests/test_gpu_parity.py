@@ -141,6 +141,16 @@ def test_wide_band_in_place_factor(flr, ctx):
     assert abs(sol.cg_iters - ref.cg_iters) <= max(5, ref.cg_iters // 50)
 
 
+def test_widest_register_panel_window(flr, ctx):
+    # bandwidth 106 (W = 107): the widest band whose factor runs in register panels with its window in
+    # LDS (every 16-wide block of the trailing triangle in use); p = 403 leaves a ragged last panel.  One
+    # ulp of y moves the oracle's beta by 8e-12 here, so the FP64 bar holds.
+    inst = _chain_plus_span(3, 0.2, 0.5, p=403, span=106)
+    sol, ref = _pair(flr, ctx, inst, tol=1e-8)
+    _check(flr, sol, ref)
+    assert abs(sol.cg_iters - ref.cg_iters) <= max(5, ref.cg_iters // 50)
+
+
 def test_all_pairs_wide(flr, ctx):
     # all-pairs with p = 150 (bw = 149, in-place factor).  At tol 1e-7 this MM trajectory is very
     # sensitive to rounding: a one-ulp change of y moves the oracle's own beta by 3e-4 and its
