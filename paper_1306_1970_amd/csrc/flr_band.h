@@ -24,6 +24,8 @@
 // steps of a sub-chunk (one row of W multipliers per step, read coalesced
 // across threads), with its loads issued a sub-chunk ahead.
 #pragma once
+#include <type_traits>
+
 #include "flr_device.h"
 
 namespace flr {
@@ -192,67 +194,85 @@ __device__ inline bool band_factor_panels(double* __restrict__ Lb, double* __res
     const int w = (p - j0) < (int64_t)NB ? (int)(p - j0) : NB;
     lds_barrier();
     if (wave == 0) {
-      double x0[NB], x1[NB];
-#pragma unroll
-      for (int jj = 0; jj < NB; ++jj) {
-        const int slot = s0 + jj < R ? s0 + jj : s0 + jj - R;
-        const int k0 = lane - jj, k1 = lane + 64 - jj;  // entries of column j0 + jj in the lane's rows
-        x0[jj] = (jj < w && k0 >= 0 && k0 < W) ? lds[slot * W + k0] : 0.0;
-        x1[jj] = (jj < w && k1 < W) ? lds[slot * W + k1] : 0.0;
-      }
-      bool bad = false;
-#pragma unroll
-      for (int jj = 0; jj < NB; ++jj) {
-        if (jj >= w) break;
-        const double piv = readlane_f64(x0[jj], jj);
-        if (!(piv > 0.0) || !isfinite(piv)) {
-          bad = true;
-          break;
-        }
-        const double ljj = sqrt(piv), rj = 1.0 / ljj;
-        if (lane == 0) sh_inv[jj] = rj;
-        const double l0 = lane > jj ? x0[jj] * rj : (lane == jj ? ljj : 0.0);
-        const double l1 = x1[jj] * rj;
-        x0[jj] = l0;
-        x1[jj] = l1;
-#pragma unroll
-        for (int c = jj + 1; c < NB; ++c) {
-          if (c < w) {
-            const double lc = readlane_f64(l0, c);
-            x0[c] = fma(-l0, lc, x0[c]);
-            x1[c] = fma(-l1, lc, x1[c]);
-          }
-        }
-      }
-      if (bad) {
-        if (lane == 0) sh_bad = 1;
-      } else {
+      // the panel in registers.  Full panels (all but possibly the last) are
+      // compiled without the per-column bounds; LDS reads are unconditional
+      // at indices clamped into the column and selected afterwards (a
+      // guarded read compiles to a branch), and ring positions wrap once at
+      // R W: the slot of column j0 + jj starts at (s0 + jj) W mod R W.
+      auto factor_panel = [&](auto full) {
+        constexpr bool F = decltype(full)::value;
+        const int ww = F ? NB : w;
+        const int RW = R * W, base = s0 * W;
+        double x0[NB], x1[NB];
 #pragma unroll
         for (int jj = 0; jj < NB; ++jj) {
-          if (lane < R) Lp[lane * LP + jj] = x0[jj];
-          if (lane + 64 < R) Lp[(lane + 64) * LP + jj] = x1[jj];
+          const int k0 = lane - jj, k1 = lane + 64 - jj;  // entries of column j0 + jj in the lane's rows
+          int a0 = base + jj * W + (k0 < 0 ? 0 : (k0 < W ? k0 : W - 1));
+          int a1 = base + jj * W + (k1 < W ? k1 : W - 1);
+          a0 = a0 >= RW ? a0 - RW : a0;
+          a1 = a1 >= RW ? a1 - RW : a1;
+          const double v0 = lds[a0], v1 = lds[a1];
+          x0[jj] = ((F || jj < ww) && k0 >= 0 && k0 < W) ? v0 : 0.0;
+          x1[jj] = ((F || jj < ww) && k1 < W) ? v1 : 0.0;
         }
-      }
+        bool bad = false;
+#pragma unroll
+        for (int jj = 0; jj < NB; ++jj) {
+          if (!F && jj >= ww) break;
+          const double piv = readlane_f64(x0[jj], jj);
+          if (!(piv > 0.0) || !isfinite(piv)) {
+            bad = true;
+            break;
+          }
+          const double ljj = sqrt(piv), rj = 1.0 / ljj;
+          if (lane == 0) sh_inv[jj] = rj;
+          const double l0 = lane > jj ? x0[jj] * rj : (lane == jj ? ljj : 0.0);
+          const double l1 = x1[jj] * rj;
+          x0[jj] = l0;
+          x1[jj] = l1;
+#pragma unroll
+          for (int c = jj + 1; c < NB; ++c) {
+            if (F || c < ww) {
+              const double lc = readlane_f64(l0, c);
+              x0[c] = fma(-l0, lc, x0[c]);
+              x1[c] = fma(-l1, lc, x1[c]);
+            }
+          }
+        }
+        if (bad) {
+          if (lane == 0) sh_bad = 1;
+        } else {
+#pragma unroll
+          for (int jj = 0; jj < NB; ++jj) {
+            if (lane < R) Lp[lane * LP + jj] = x0[jj];
+            if (lane + 64 < R) Lp[(lane + 64) * LP + jj] = x1[jj];
+          }
+        }
+      };
+      if (w == NB)
+        factor_panel(std::integral_constant<bool, true>());
+      else
+        factor_panel(std::integral_constant<bool, false>());
     }
     lds_barrier();
     if (sh_bad) return false;
     if (wave == 0) {
-      // the panel's slots take the columns entering the window, then the
-      // loads for the next panel go out
+      // the panel's slots take the columns entering the window (entry e of
+      // them at (s0 W + e) mod R W), then the loads for the next panel go out
+      const int RW = R * W;
+      const int64_t left = pw - (j0 + R) * W, left2 = left - (int64_t)NB * W;
+      const int lim = left < (int64_t)NB * W ? (int)(left > 0 ? left : 0) : NB * W;
+      const int lim2 = left2 < (int64_t)NB * W ? (int)(left2 > 0 ? left2 : 0) : NB * W;
 #pragma unroll
       for (int q = 0; q < NXT; ++q) {
-        const int e = lane + 64 * q;
-        if (e < NB * W && (j0 + R) * W + e < pw) {
-          const int ce = e / W;
-          const int slot = s0 + ce < R ? s0 + ce : s0 + ce - R;
-          lds[slot * W + (e - ce * W)] = nxt[q];
-        }
+        const int e = lane + 64 * q, a = s0 * W + e;
+        if (e < lim) lds[a >= RW ? a - RW : a] = nxt[q];
       }
+      const double* src = Lb + (j0 + NB + R) * W;
 #pragma unroll
       for (int q = 0; q < NXT; ++q) {
         const int e = lane + 64 * q;
-        const int64_t g = (j0 + NB + R) * W + e;
-        nxt[q] = (e < NB * W && g < pw) ? Lb[g] : 0.0;
+        nxt[q] = e < lim2 ? src[e] : 0.0;
       }
     } else {
       // the panel's columns of L: Lb scaled by 1/L_jj below the diagonal,
